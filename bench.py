@@ -1,0 +1,249 @@
+"""Benchmark: forward + backward ms per view for 1M clustered Gaussians at 1600x1064.
+
+One step = one view through the whole path: projection (gs_preprocess), depth sort (gs_sort),
+forward raster (gs_raster_fwd), backward raster (gs_raster_bwd) and projection backward
+(gs_preprocess_bwd), with dL/dC ~ U[-1, 1] (the paper's backward protocol, Sec. 4). Inputs are
+resident in HBM before the timed region. The headline is the FP16-framebuffer path; the FP32
+path is timed the same way and reported beside it.
+
+Prints one JSON line (rank 0). Single GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FLOPs per fragment of the method's own arithmetic:
+FLOP_FWD_PER_COVERED = 24   # alpha of one fragment + the blend of Eq. 2
+FLOP_BWD_PER_LIVE = 72      # alpha, Eqs. 3/5/6/7, the chain rule to 9 parameters, their reduction
+PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
+    ap.add_argument("--formats", default="f16,f32")
+    ap.add_argument("--reduce", default="hybrid")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-blocks", type=int, default=12)
+    ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")
+    return ap.parse_args()
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2505_18764_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2505_18764_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_key):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they match this build."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    e = d.get(kernel_key)
+    if not e or e.get("source_hash") != _src_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
+              "component (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2505_18764_amd import render as R
+
+    dev = torch.device("cuda:0")
+    c3 = dict(synth.CFG3)
+    if args.n:
+        c3["n"] = args.n
+    W, H = c3["width"], c3["height"]
+    sc = synth.scene3d(c3["n"], seed=c3["seed"])
+    cam = synth.camera_front(W, H, c3["fx"])
+    G = synth.image_grad(W, H, c3["grad_seed"])
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    inp = [t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh)]
+    Gd = t(G)
+    torch.cuda.synchronize()
+
+    def run_format(fmt, reduce_mode, t_min_fwd=0.0, steps=args.steps, warmup=args.warmup):
+        cfg = R.RasterConfig(fb_format=fmt, reduce_mode=reduce_mode, t_min_fwd=t_min_fwd)
+        ws = R.Workspace(dev)
+        # preallocated outputs: the timed steps allocate nothing
+        p = R.project(*inp, cam, cfg, ws)
+        f = R.raster_forward(p, cfg, ws)
+        g2 = R.raster_backward(p, f["fb"], Gd, cfg, ws)
+        g3 = R.project_backward(*inp, cam, cfg, g2)
+        torch.cuda.synchronize()
+        # fragment counts of this workload (instrumented run, outside the timed region)
+        st = R.new_stats(dev)
+        R.raster_forward(p, cfg, ws, fb=f["fb"], image=f["image"], T=f["T"], stats=st)
+        R.raster_backward(p, f["fb"], Gd, cfg, ws, stats=st, out=g2)
+        torch.cuda.synchronize()
+        stats = R.read_stats(st)
+        nvis = int(p.n_visible.item())
+
+        def step(ev=None):
+            rec = (lambda i: ev[i].record()) if ev else (lambda i: None)
+            rec(0)
+            q = R.project(*inp, cam, cfg, ws, sort=False)
+            rec(1)
+            R.sort_(q, ws)
+            rec(2)
+            R.raster_forward(q, cfg, ws, fb=f["fb"], image=f["image"], T=f["T"])
+            rec(3)
+            R.raster_backward(q, f["fb"], Gd, cfg, ws, out=g2)
+            rec(4)
+            R.project_backward(*inp, cam, cfg, g2, out=g3)
+            rec(5)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(evs[i])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        names = ["preprocess", "sort", "raster_fwd", "raster_bwd", "preprocess_bwd"]
+        per = {k: float(np.median([e[j].elapsed_time(e[j + 1]) for e in evs]))
+               for j, k in enumerate(names)}
+        total = float(np.median([e[0].elapsed_time(e[5]) for e in evs]))
+        return dict(fmt=fmt, ms_per_view=total, wall_ms_per_view=wall, stages_ms=per,
+                    stats=stats, n_visible=nvis, ws_bytes=ws.nbytes)
+
+    results = {}
+    for fmt in args.formats.split(","):
+        results[fmt] = run_format(fmt, args.reduce)
+    head_fmt = "f16" if "f16" in results else list(results)[0]
+    head = results[head_fmt]
+    st = head["stats"]
+    F, Lv = st["fwd_covered"], st["bwd_live"]
+    fwd_ms, bwd_ms = head["stages_ms"]["raster_fwd"], head["stages_ms"]["raster_bwd"]
+    roof = {}
+    for name, ms, flops, key in (("raster_fwd", fwd_ms, F * FLOP_FWD_PER_COVERED, "k_raster_fwd"),
+                                 ("raster_bwd", bwd_ms, Lv * FLOP_BWD_PER_LIVE, "k_raster_bwd")):
+        ach = flops / (ms * 1e-3) / 1e12
+        roof[name] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                      "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                      "traffic": _traffic(key), "flops_per_launch": flops, "ms": round(ms, 4)}
+    dom = "raster_fwd" if fwd_ms >= bwd_ms else "raster_bwd"
+
+    extra = {}
+    if args.variants:
+        for mode in ("naive", "quad", "wave", "hybrid", "hybrid_lane"):
+            r = run_format(head_fmt, mode, steps=max(3, args.steps // 4), warmup=1)
+            s = r["stats"]
+            extra[f"reduce_{mode}"] = {"raster_bwd_ms": r["stages_ms"]["raster_bwd"],
+                                       "atomic_rate": s["bwd_atomic_sets"] / max(1, s["bwd_live"])}
+        r = run_format(head_fmt, args.reduce, t_min_fwd=float(np.float32(1e-4)),
+                       steps=max(3, args.steps // 2), warmup=1)
+        extra["fwd_tcull_ms_per_view"] = r["ms_per_view"]
+        extra["fwd_tcull_stages_ms"] = r["stages_ms"]
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(sc, cam, G, args.cpu_blocks)
+
+    line = {
+        "metric": "fwd+bwd ms/view @1M splats 1600x1064 (FP16 vs FP32 FB); p50/p99 latency",
+        "value": round(head["ms_per_view"], 4),
+        "unit": "ms/view",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_view"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{c3['n']} clustered 3D Gaussians (SH deg 3), {W}x{H}, "
+                               f"fx={c3['fx']}, dL/dC~U[-1,1]; framebuffer {head_fmt}, "
+                               f"reduction {args.reduce}, paper mode (no forward T-cull)",
+                   "fb_format": head_fmt, "n": c3["n"], "width": W, "height": H},
+        "views_per_s": round(1e3 / head["ms_per_view"], 2),
+        "formats": {k: {"ms_per_view": round(v["ms_per_view"], 4),
+                        "stages_ms": {s: round(x, 4) for s, x in v["stages_ms"].items()},
+                        "wall_ms_per_view": round(v["wall_ms_per_view"], 4)}
+                    for k, v in results.items()},
+        "fragments": {"covered": F, "live": Lv, "n_visible": head["n_visible"],
+                      "covered_per_s": round(F / (fwd_ms * 1e-3), 1),
+                      "live_per_s": round(Lv / (bwd_ms * 1e-3), 1),
+                      "atomic_rate": round(st["bwd_atomic_sets"] / max(1, Lv), 5),
+                      "cohesion": round(st["bwd_cohesive"] / max(1, st["bwd_wave_reductions"] +
+                                                                   st["bwd_quad_reductions"]), 4)},
+        "roofline": dict(roof[dom], kernel=dom),
+        "roofline_kernels": roof,
+        "workspace_bytes": head["ws_bytes"],
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(sc, cam, G, blocks):
+    """The FP64 oracle timed on this host on a bounded sample of the same view: the projection of
+    all Gaussians, the raster forward + backward on `blocks` random 32x32 pixel blocks (all
+    Gaussians, seeded choice), and the projection backward on 2 % of the Gaussians, each scaled to
+    a full view."""
+    import oracle
+    nth = os.cpu_count() or 1
+    cfg = oracle.OracleConfig(nthreads=nth)
+    t0 = time.perf_counter()
+    pre = oracle.preprocess(sc, cam, cfg)
+    t_pre = time.perf_counter() - t0
+    order = oracle.visible_order(pre["keys"])
+    m2, cn, rgb = (pre["means2d"].astype(np.float32), pre["conic"].astype(np.float32),
+                   pre["rgb"].astype(np.float32))
+    g = np.random.default_rng(77)
+    W, H = cam.width, cam.height
+    t_r = 0.0
+    px = 0
+    for _ in range(blocks):
+        x0, y0 = int(g.integers(0, W - 32)), int(g.integers(0, H - 32))
+        t0 = time.perf_counter()
+        oracle.raster(m2, cn, sc.opacities, rgb, order, W, H, crop=(x0, y0, 32, 32), dL_dimg=G,
+                      cfg=cfg)
+        t_r += time.perf_counter() - t0
+        px += 32 * 32
+    sub = g.choice(sc.n, size=max(1, sc.n // 50), replace=False)
+    import synth
+    s2 = synth.Scene(means3d=sc.means3d[sub], scales=sc.scales[sub], quats=sc.quats[sub],
+                     opacities=sc.opacities[sub], sh=sc.sh[sub], sh_degree=sc.sh_degree)
+    gg = g.normal(size=(len(sub), 9))
+    t0 = time.perf_counter()
+    oracle.preprocess_vjp(s2, cam, gg[:, 0:2], gg[:, 2:5], gg[:, 6:9], gg[:, 5], cfg)
+    t_vjp = (time.perf_counter() - t0) * sc.n / len(sub)
+    total_s = t_pre + t_r * (W * H / px) + t_vjp
+    return {"value": round(total_s * 1e3, 1), "unit": "ms/view", "cores": nth, "kind": "oracle",
+            "sample": f"FP64 oracle: projection of all {sc.n} Gaussians ({t_pre:.2f} s); raster "
+                      f"fwd+bwd on {blocks} random 32x32 blocks ({px} px, {t_r:.2f} s) scaled by "
+                      f"{W * H / px:.0f}x; projection backward on {len(sub)} Gaussians scaled by "
+                      f"{sc.n / len(sub):.0f}x"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,264 @@
+/*
+ * gsr.h -- C ABI of libgsr.so, the MI355X (gfx950) differentiable Gaussian-splat rasterizer.
+ *
+ * Method: "Efficient Differentiable Hardware Rasterization for 3D Gaussian Splatting"
+ * (arXiv 2505.18764). The path is: projection of 3D Gaussians to 2D splats (Sec. 2.1.2), a depth
+ * sort of all splats (Sec. 1, Sec. 4.1), ordered alpha compositing into a fixed-size per-pixel
+ * framebuffer (Eq. 2), the front-to-back gradient procedure that rematerialises each fragment's
+ * gradient from the stored framebuffer state (Sec. 3.1, Procedure 1), the quad/wave gradient
+ * reduction before global atomics (Sec. 3.2, Procedure 2), and the backward of the projection
+ * (Sec. 2.1.3, the "dedicated subsequent pass").
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers to caller-owned, contiguous, row-major memory
+ *     (FP32 unless typed otherwise). The library never allocates device memory; scratch comes from
+ *     the caller's workspace `ws` of `ws_bytes` bytes (size it with gs_workspace_size()).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Work is enqueued
+ *     asynchronously; no entry point synchronises the device or the stream.
+ *   - Arguments are validated on the host before any HIP call. On failure the call returns a
+ *     nonzero status, enqueues nothing, and gs_last_error() describes the problem (thread-local).
+ *     GS_ERR_HIP means a launch failed; its message carries the HIP error string.
+ *   - n = 0 is valid everywhere; images are then 0 with T = 1 and gradient outputs are zero.
+ *   - Gradient outputs are overwritten (zero-filled first), as the buffers in Procedure 2 start
+ *     at zero.
+ *   - Width and height are 1 .. 16384; n is 0 .. 2^28.
+ *   - Nothing here is thread-safe across calls that share a workspace.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_ABI_VERSION 1
+
+enum gs_status {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARGUMENT = 1,
+    GS_ERR_CAPACITY = 2,        /* workspace or pair buffer too small */
+    GS_ERR_UNSUPPORTED = 3,
+    GS_ERR_HIP = 4
+};
+
+/* Render-target formats of the framebuffer state (Sec. 3.3, mixed-precision rendering). */
+enum gs_fb_format {
+    GS_FB_F32 = 0,      /* 4 x fp32 per pixel (16 B) */
+    GS_FB_F16 = 1,      /* 4 x IEEE half, round to nearest even (8 B) */
+    GS_FB_UNORM16 = 2,  /* 4 x round(clamp(x,0,1) * 65535) (8 B); splat colours saturate to 1 */
+    GS_FB_BF16 = 3,     /* 4 x bfloat16, round to nearest even (8 B) */
+    GS_FB_UNORM8 = 4    /* 4 x round(clamp(x,0,1) * 255) (4 B); splat colours saturate to 1 */
+};
+
+/* When the per-pixel state is rounded to the framebuffer format. */
+enum gs_fb_round {
+    GS_ROUND_AT_REST = 0,       /* state is FP32 while a tile is resident on chip; rounded when
+                                   written back to the framebuffer (and read back rounded) */
+    GS_ROUND_PER_FRAGMENT = 1   /* rounded after every fragment store, like a hardware render
+                                   target that blends in its own format */
+};
+
+/* Gradient reduction before the global atomics (Sec. 3.2, Procedure 2, Table 1). */
+enum gs_reduce_mode {
+    GS_REDUCE_NAIVE = 0,        /* one atomicAdd per live fragment and parameter */
+    GS_REDUCE_QUAD = 1,         /* sum over the 2x2 quad; the lowest live lane of each quad adds */
+    GS_REDUCE_WAVE = 2,         /* wave sum when >= X lanes are live, else per-fragment atomics */
+    GS_REDUCE_HYBRID = 3,       /* Procedure 2: wave sum when all live lanes hold one splat and
+                                   >= X are live, else quad sums */
+    GS_REDUCE_HYBRID_LANE = 4   /* Procedure 2 applied once per splat per wave after each lane
+                                   has summed its own pixels' fragments in registers */
+};
+
+enum gs_flags {
+    GS_FLAG_STATS = 1           /* count fragments, atomics and reductions into gs_stats */
+};
+
+/* Pinhole camera. viewmat is the 3x4 world->camera matrix [R|t], row-major; the camera looks
+ * along +z, x to the right, y down; fx, fy, cx, cy in pixels; pixel (x, y) has its centre at
+ * (x + 0.5, y + 0.5). Splats with view depth below znear are culled. */
+typedef struct gs_camera {
+    float viewmat[12];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float znear;
+    float reserved;
+} gs_camera;
+
+/* Method constants and switches. gs_config_default() fills in the paper's values. */
+typedef struct gs_config {
+    float alpha_min;        /* 1/255: fragments below it are discarded (Sec. 2.1.2) */
+    float alpha_max;        /* 0.99: clamp that keeps 1 - alpha away from 0 (reading) */
+    float t_min_fwd;        /* 0: the forward does not T-cull, as hardware blending cannot
+                               (Sec. 2.1.4); > 0 enables forward T-culling */
+    float t_min_bwd;        /* 1e-4: T-culling in the backward (Sec. 2.1.4, Procedure 1) */
+    float eps2d;            /* 0.3 px^2 dilation of the 2D covariance (reading) */
+    int32_t sh_degree;      /* 0..3; sh arrays hold (sh_degree + 1)^2 coefficients per colour */
+    int32_t fb_format;      /* enum gs_fb_format */
+    int32_t fb_round;       /* enum gs_fb_round */
+    int32_t reduce_mode;    /* enum gs_reduce_mode */
+    int32_t reduce_threshold; /* X of Procedure 2: minimum live lanes for the wave path (8) */
+    int32_t flags;          /* enum gs_flags */
+    int32_t reserved[5];
+} gs_config;
+
+/* Device-side counters (add-only; zero them before the calls you want to count). */
+typedef struct gs_stats {
+    unsigned long long fwd_queued;      /* (tile, splat) pairs taken from the sorted list */
+    unsigned long long fwd_evaluated;   /* (pixel, splat) alphas evaluated */
+    unsigned long long fwd_covered;     /* fragments blended */
+    unsigned long long bwd_queued;
+    unsigned long long bwd_evaluated;
+    unsigned long long bwd_live;        /* fragments that passed both culls of Procedure 1 */
+    unsigned long long bwd_atomic_sets; /* leader lanes that issued one set of gradient atomics */
+    unsigned long long bwd_wave_reductions;
+    unsigned long long bwd_quad_reductions;
+    unsigned long long bwd_cohesive;    /* reductions whose live lanes all held one splat */
+    unsigned long long reserved[6];
+} gs_stats;
+
+/* Workspace users (argument `op` of gs_workspace_size). */
+enum gs_op {
+    GS_OP_PREPROCESS = 0,
+    GS_OP_SORT = 1,
+    GS_OP_RASTER_FWD = 2,
+    GS_OP_RASTER_BWD = 3,
+    GS_OP_PREPROCESS_BWD = 4,
+    GS_OP_PREPARE_2D = 5,
+    GS_OP_ALL = 6           /* enough for every op above (one shared workspace) */
+};
+
+/* Thread-local description of the last failure ("" when none). */
+const char* gs_last_error(void);
+
+/* GSR_ABI_VERSION of the built library. */
+int32_t gs_version(void);
+
+/* Paper defaults: alpha_min 1/255, alpha_max 0.99, t_min_fwd 0, t_min_bwd 1e-4, eps2d 0.3,
+ * sh_degree 3, F32 framebuffer rounded at rest, HYBRID reduction with X = 8. */
+void gs_config_default(gs_config* cfg);
+
+/* Bytes of scratch the op needs for n splats at width x height. Pure host function of its
+ * arguments (no HIP call); 0 for invalid arguments. Every buffer in the library has a size that
+ * is a closed form of (n, width, height, format): this is what a server admits requests by. */
+size_t gs_workspace_size(int32_t op, int32_t n, int32_t width, int32_t height,
+                         const gs_config* cfg);
+
+/* Bytes of the framebuffer (width * height pixels x 4 channels in cfg->fb_format). */
+size_t gs_framebuffer_size(int32_t width, int32_t height, int32_t fb_format);
+
+/*
+ * Projection (Sec. 2.1.1-2.1.2): for each Gaussian i, Sigma_3D = R S S^T R^T from the quaternion
+ * quats[i] = (w, x, y, z) (normalised here) and scales[i] (> 0); t = R_view mu + t_view;
+ * mean2d = (fx tx/tz + cx, fy ty/tz + cy); Sigma_2D = J W Sigma_3D W^T J^T + eps2d I with J the
+ * Jacobian of the perspective map; conic = Sigma_2D^{-1} as (a, b, c) with
+ * q = a dx^2 + 2 b dx dy + c dy^2; colour = max(0, sum_k Y_k(dir) sh[i][k] + 0.5) with real SH of
+ * degree cfg->sh_degree at the unit direction from the camera centre to mu.
+ * Frustum culling (Sec. 4.1): a splat is culled when tz < znear, opacity < alpha_min, the 2D
+ * covariance is not positive definite, or the bounding box of its alpha >= alpha_min ellipse
+ * holds no pixel centre of the image.
+ * Inputs [n]: means3d [n,3], scales [n,3], quats [n,4], opacities [n] (in [0,1]),
+ *   sh [n, (sh_degree+1)^2, 3].
+ * Outputs by splat id: means2d [n,2], conics [n,3], rgb [n,3], depth [n] (fp32 view depth; 0 if
+ *   culled; culled splats also get zero means2d/conics/rgb).
+ * Sort input (GPU-driven culling, Sec. 4.1): keys [n], ids [n] hold the visible splats first, in
+ *   id order, as (bits of fp32(tz) with tz evaluated in FP64, id), then the culled splats in id
+ *   order as (0xFFFFFFFF, id); n_visible [1] (device int32) is the number of visible splats.
+ *   The compaction is deterministic (a prefix sum, no atomics).
+ * Workspace: gs_workspace_size(GS_OP_PREPROCESS, n, ...).
+ */
+int gs_preprocess(const gs_camera* cam, const gs_config* cfg, int32_t n,
+                  const float* means3d, const float* scales, const float* quats,
+                  const float* opacities, const float* sh,
+                  float* means2d, float* conics, float* rgb, float* depth,
+                  uint32_t* keys, int32_t* ids, int32_t* n_visible,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Sort input for splats that are already 2D (Sec. 2.1.2 with the projection given): the key of
+ * splat i is the order-preserving uint32 of fp32 depth[i]; a splat is culled when it cannot put a
+ * fragment on the image (opacity < alpha_min, conic not positive definite, or the bounding box of
+ * its alpha >= alpha_min ellipse holds no pixel centre). keys/ids/n_visible as gs_preprocess
+ * (visible first in id order, then culled with key 0xFFFFFFFF). Only cam->width and cam->height
+ * are read. Workspace: gs_workspace_size(GS_OP_PREPARE_2D, n, ...).
+ */
+int gs_prepare_2d(const gs_camera* cam, const gs_config* cfg, int32_t n,
+                  const float* means2d, const float* conics, const float* opacities,
+                  const float* depth, uint32_t* keys, int32_t* ids, int32_t* n_visible,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Depth sort (Sec. 1, Sec. 4.1): stable ascending sort of the first *n_visible (key, id) pairs in
+ * place, by the full 32-bit key; equal keys keep their input order (so, after gs_preprocess,
+ * ties are broken by id). The length is read on the device (dynamic-length sort after culling,
+ * no host readback); entries from *n_visible to n are left in place. Afterwards ids[0..n) is
+ * still a permutation of 0..n-1. Workspace: gs_workspace_size(GS_OP_SORT, n, ...).
+ */
+int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible,
+            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Forward rasterization (Eq. 2): for every pixel, the splats in sorted_ids[0 .. *n_visible) are
+ * composited front to back: alpha = min(alpha_max, o exp(-q/2)), fragments with
+ * alpha < alpha_min discarded, C += T alpha c, T *= 1 - alpha (optionally T-culled when
+ * cfg->t_min_fwd > 0). The per-pixel state (C, T) is rounded to cfg->fb_format per cfg->fb_round
+ * and written to the framebuffer `fb` (gs_framebuffer_size bytes, [H][W][4] in that format).
+ * In the unorm formats splat colours saturate to 1 (Sec. 3.3).
+ * Inputs [n] by splat id: means2d [n,2], conics [n,3], opacities [n], rgb [n,3];
+ *   sorted_ids [n] (a permutation of 0..n-1, as gs_sort leaves it), n_visible [1] device int32.
+ * Outputs: fb; out_rgb [3,H,W] and out_T [H,W] (fp32 copies of the stored state, nullable);
+ *   out_coverage [H,W] int32 fragments blended per pixel (nullable); stats (nullable, counted
+ *   with GS_FLAG_STATS).
+ * Workspace: gs_workspace_size(GS_OP_RASTER_FWD, n, W, H, cfg).
+ */
+int gs_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
+                  const int32_t* sorted_ids, const int32_t* n_visible,
+                  const float* means2d, const float* conics, const float* opacities,
+                  const float* rgb, void* fb, float* out_rgb, float* out_T,
+                  int32_t* out_coverage, gs_stats* stats, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/*
+ * Backward rasterization (Sec. 3.1, Procedure 1 ComputeGradient; Sec. 3.2, Procedure 2
+ * ReduceGradient): the state (C', T) starts at (C from `fb`, 1); the splats are walked in the
+ * forward's order; for each fragment: cull if alpha < alpha_min; cull if T < t_min_bwd (state
+ * left unchanged); otherwise dL/dc = dL/dC alpha T (Eq. 3), dL/dalpha = dL/dC . (c T - C')/(1 -
+ * alpha) (Eq. 7), (C', T) <- (C' - T alpha c, T (1 - alpha)) (Eqs. 5-6), and the chain rule to
+ * (mean2d, conic, opacity, rgb); then the reduction of cfg->reduce_mode with threshold X and FP32
+ * global atomics.
+ * Inputs: as gs_raster_fwd plus fb (the forward's framebuffer, same cfg) and dL_dimage [3,H,W].
+ * Outputs (overwritten) [n] by splat id: dL_dmeans2d [n,2], dL_dconics [n,3] (w.r.t. a, b, c),
+ *   dL_dopacities [n], dL_drgb [n,3]; out_live [H,W] int32 live fragments per pixel (nullable);
+ *   stats (nullable).
+ * Workspace: gs_workspace_size(GS_OP_RASTER_BWD, n, W, H, cfg).
+ */
+int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
+                  const int32_t* sorted_ids, const int32_t* n_visible,
+                  const float* means2d, const float* conics, const float* opacities,
+                  const float* rgb, const void* fb, const float* dL_dimage,
+                  float* dL_dmeans2d, float* dL_dconics, float* dL_dopacities, float* dL_drgb,
+                  int32_t* out_live, gs_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Backward of the projection (Sec. 2.1.3: "a dedicated subsequent pass"): from the gradients
+ * w.r.t. the 2D splat (mean2d, conic, rgb, opacity) to those w.r.t. the 3D Gaussian, including
+ * the view-direction term of the SH colour and the quaternion normalisation. Recomputes the
+ * forward from the same inputs as gs_preprocess. Culled splats get zero gradients.
+ * Outputs (overwritten): dL_dmeans3d [n,3], dL_dscales [n,3], dL_dquats [n,4],
+ *   dL_dopacities [n], dL_dsh [n,(sh_degree+1)^2,3]. Workspace: none.
+ */
+int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
+                      const float* means3d, const float* scales, const float* quats,
+                      const float* opacities, const float* sh,
+                      const float* dL_dmeans2d, const float* dL_dconics, const float* dL_drgb,
+                      const float* dL_dopacities2d,
+                      float* dL_dmeans3d, float* dL_dscales, float* dL_dquats,
+                      float* dL_dopacities, float* dL_dsh, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

@@ -1,0 +1,287 @@
+// api.hip -- the extern "C" boundary of libgsr.so: host-side validation, workspace sizing and
+// error reporting around the launchers. No exception crosses this boundary; no entry point
+// allocates device memory or synchronises.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return GS_OK;
+}
+
+int hip_status(hipError_t e, const char* where) {
+    if (e == hipSuccess) return ok();
+    return fail(GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int32_t MAX_N = 1 << 28;
+constexpr int32_t MAX_DIM = 16384;
+
+int check_n(int32_t n) {
+    if (n < 0 || n > MAX_N) return fail(GS_ERR_INVALID_ARGUMENT, "n = %d outside 0..2^28", n);
+    return GS_OK;
+}
+
+int check_cam(const gs_camera* cam) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    if (cam->width < 1 || cam->width > MAX_DIM || cam->height < 1 || cam->height > MAX_DIM)
+        return fail(GS_ERR_INVALID_ARGUMENT, "image %d x %d outside 1..16384", cam->width,
+                    cam->height);
+    for (int i = 0; i < 12; ++i)
+        if (!isfinite(cam->viewmat[i])) return fail(GS_ERR_INVALID_ARGUMENT, "viewmat not finite");
+    if (!(isfinite(cam->fx) && isfinite(cam->fy) && isfinite(cam->cx) && isfinite(cam->cy)) ||
+        !(cam->fx > 0.f && cam->fy > 0.f))
+        return fail(GS_ERR_INVALID_ARGUMENT, "focal lengths must be finite and > 0");
+    if (!(cam->znear > 0.f) || !isfinite(cam->znear))
+        return fail(GS_ERR_INVALID_ARGUMENT, "znear must be finite and > 0");
+    return GS_OK;
+}
+
+int check_dims(int32_t width, int32_t height) {
+    if (width < 1 || width > MAX_DIM || height < 1 || height > MAX_DIM)
+        return fail(GS_ERR_INVALID_ARGUMENT, "image %d x %d outside 1..16384", width, height);
+    return GS_OK;
+}
+
+int check_cfg(const gs_config* c) {
+    if (!c) return fail(GS_ERR_INVALID_ARGUMENT, "config is NULL");
+    if (!(c->alpha_min > 0.f && c->alpha_min < 1.f))
+        return fail(GS_ERR_INVALID_ARGUMENT, "alpha_min must be in (0, 1)");
+    if (!(c->alpha_max > c->alpha_min && c->alpha_max < 1.f))
+        return fail(GS_ERR_INVALID_ARGUMENT, "alpha_max must be in (alpha_min, 1)");
+    if (!(c->t_min_fwd >= 0.f && c->t_min_fwd < 1.f))
+        return fail(GS_ERR_INVALID_ARGUMENT, "t_min_fwd must be in [0, 1)");
+    if (!(c->t_min_bwd >= 0.f && c->t_min_bwd < 1.f))
+        return fail(GS_ERR_INVALID_ARGUMENT, "t_min_bwd must be in [0, 1)");
+    if (!(c->eps2d >= 0.f) || !isfinite(c->eps2d))
+        return fail(GS_ERR_INVALID_ARGUMENT, "eps2d must be finite and >= 0");
+    if (c->sh_degree < 0 || c->sh_degree > 3)
+        return fail(GS_ERR_INVALID_ARGUMENT, "sh_degree %d outside 0..3", c->sh_degree);
+    if (c->fb_format < GS_FB_F32 || c->fb_format > GS_FB_UNORM8)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown fb_format %d", c->fb_format);
+    if (c->fb_round != GS_ROUND_AT_REST && c->fb_round != GS_ROUND_PER_FRAGMENT)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown fb_round %d", c->fb_round);
+    if (c->reduce_mode < GS_REDUCE_NAIVE || c->reduce_mode > GS_REDUCE_HYBRID_LANE)
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown reduce_mode %d", c->reduce_mode);
+    if (c->reduce_threshold < 0 || c->reduce_threshold > 64)
+        return fail(GS_ERR_INVALID_ARGUMENT, "reduce_threshold %d outside 0..64", c->reduce_threshold);
+    if (c->flags & ~GS_FLAG_STATS) return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", c->flags);
+    return GS_OK;
+}
+
+#define GSR_TRY(x)                \
+    do {                          \
+        int _rc = (x);            \
+        if (_rc != GS_OK) return _rc; \
+    } while (0)
+
+#define GSR_NEED(p)                                                              \
+    do {                                                                         \
+        if (!(p)) return fail(GS_ERR_INVALID_ARGUMENT, "%s is NULL", #p);       \
+    } while (0)
+
+int check_ws(void* ws, size_t have, size_t need) {
+    if (need == 0) return GS_OK;
+    if (!ws) return fail(GS_ERR_INVALID_ARGUMENT, "workspace is NULL (%zu bytes needed)", need);
+    if (have < need)
+        return fail(GS_ERR_CAPACITY, "workspace has %zu bytes, %zu needed", have, need);
+    if (((uintptr_t)ws) % 256 != 0) return fail(GS_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+    return GS_OK;
+}
+
+size_t preprocess_ws(int32_t n) { return gsr::align_up((size_t)n * 4) + gsr::compact_ws_bytes(n); }
+
+}  // namespace
+
+extern "C" {
+
+const char* gs_last_error(void) { return g_err.c_str(); }
+
+int32_t gs_version(void) { return GSR_ABI_VERSION; }
+
+void gs_config_default(gs_config* c) {
+    if (!c) return;
+    *c = gs_config{};
+    c->alpha_min = 1.0f / 255.0f;
+    c->alpha_max = 0.99f;
+    c->t_min_fwd = 0.0f;
+    c->t_min_bwd = 1e-4f;
+    c->eps2d = 0.3f;
+    c->sh_degree = 3;
+    c->fb_format = GS_FB_F32;
+    c->fb_round = GS_ROUND_AT_REST;
+    c->reduce_mode = GS_REDUCE_HYBRID;
+    c->reduce_threshold = 8;
+    c->flags = 0;
+}
+
+size_t gs_framebuffer_size(int32_t width, int32_t height, int32_t fb_format) {
+    if (width < 1 || width > MAX_DIM || height < 1 || height > MAX_DIM) return 0;
+    if (fb_format < GS_FB_F32 || fb_format > GS_FB_UNORM8) return 0;
+    return (size_t)width * height * gsr::fb_bytes_per_pixel(fb_format);
+}
+
+size_t gs_workspace_size(int32_t op, int32_t n, int32_t width, int32_t height, const gs_config* cfg) {
+    if (n < 0 || n > MAX_N) return 0;
+    (void)width;
+    (void)height;
+    (void)cfg;
+    switch (op) {
+    case GS_OP_PREPROCESS:
+    case GS_OP_PREPARE_2D: return preprocess_ws(n);
+    case GS_OP_SORT: return gsr::sort_ws_bytes(n, 4);
+    case GS_OP_RASTER_FWD: return gsr::raster_ws_bytes(n, false);
+    case GS_OP_RASTER_BWD: return gsr::raster_ws_bytes(n, true);
+    case GS_OP_PREPROCESS_BWD: return 0;
+    case GS_OP_ALL: {
+        size_t m = preprocess_ws(n);
+        size_t s = gsr::sort_ws_bytes(n, 4);
+        size_t r = gsr::raster_ws_bytes(n, true);
+        if (s > m) m = s;
+        if (r > m) m = r;
+        return m;
+    }
+    default: return 0;
+    }
+}
+
+int gs_preprocess(const gs_camera* cam, const gs_config* cfg, int32_t n, const float* means3d,
+                  const float* scales, const float* quats, const float* opacities, const float* sh,
+                  float* means2d, float* conics, float* rgb, float* depth, uint32_t* keys,
+                  int32_t* ids, int32_t* n_visible, void* ws, size_t ws_bytes, void* stream) {
+    GSR_TRY(check_cam(cam));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    if (n > 0) {
+        GSR_NEED(means3d); GSR_NEED(scales); GSR_NEED(quats); GSR_NEED(opacities); GSR_NEED(sh);
+        GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(rgb); GSR_NEED(depth); GSR_NEED(keys);
+        GSR_NEED(ids);
+        GSR_TRY(check_ws(ws, ws_bytes, preprocess_ws(n)));
+    }
+    const gsr::CamDev cd = gsr::make_cam(*cam);
+    return hip_status(gsr::launch_preprocess(cd, *cfg, n, means3d, scales, quats, opacities, sh,
+                                             means2d, conics, rgb, depth, keys, ids, n_visible, ws,
+                                             (hipStream_t)stream),
+                      "gs_preprocess");
+}
+
+int gs_prepare_2d(const gs_camera* cam, const gs_config* cfg, int32_t n, const float* means2d,
+                  const float* conics, const float* opacities, const float* depth, uint32_t* keys,
+                  int32_t* ids, int32_t* n_visible, void* ws, size_t ws_bytes, void* stream) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    GSR_TRY(check_dims(cam->width, cam->height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    if (n > 0) {
+        GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(depth);
+        GSR_NEED(keys); GSR_NEED(ids);
+        GSR_TRY(check_ws(ws, ws_bytes, preprocess_ws(n)));
+    }
+    return hip_status(gsr::launch_prepare_2d(cam->width, cam->height, *cfg, n, means2d, conics,
+                                             opacities, depth, keys, ids, n_visible, ws,
+                                             (hipStream_t)stream),
+                      "gs_prepare_2d");
+}
+
+int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible, void* ws,
+            size_t ws_bytes, void* stream) {
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    if (n == 0) return ok();
+    GSR_NEED(keys);
+    GSR_NEED(ids);
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::sort_ws_bytes(n, 4)));
+    return hip_status(gsr::launch_sort_u32(n, keys, ids, n_visible, ws, (hipStream_t)stream),
+                      "gs_sort");
+}
+
+int gs_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* sorted_ids,
+                  const int32_t* n_visible, const float* means2d, const float* conics,
+                  const float* opacities, const float* rgb, void* fb, float* out_rgb, float* out_T,
+                  int32_t* out_coverage, gs_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    GSR_TRY(check_dims(cam->width, cam->height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    GSR_NEED(fb);
+    if (n > 0) {
+        GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
+    }
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, false)));
+    return hip_status(gsr::launch_raster_fwd(*cfg, cam->width, cam->height, n, sorted_ids,
+                                             n_visible, means2d, conics, opacities, rgb, fb,
+                                             out_rgb, out_T, out_coverage, stats, ws,
+                                             (hipStream_t)stream),
+                      "gs_raster_fwd");
+}
+
+int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* sorted_ids,
+                  const int32_t* n_visible, const float* means2d, const float* conics,
+                  const float* opacities, const float* rgb, const void* fb, const float* dL_dimage,
+                  float* dL_dmeans2d, float* dL_dconics, float* dL_dopacities, float* dL_drgb,
+                  int32_t* out_live, gs_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    GSR_TRY(check_dims(cam->width, cam->height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    GSR_NEED(fb);
+    GSR_NEED(dL_dimage);
+    if (n > 0) {
+        GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
+        GSR_NEED(dL_dmeans2d); GSR_NEED(dL_dconics); GSR_NEED(dL_dopacities); GSR_NEED(dL_drgb);
+    }
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, true)));
+    return hip_status(gsr::launch_raster_bwd(*cfg, cam->width, cam->height, n, sorted_ids,
+                                             n_visible, means2d, conics, opacities, rgb, fb,
+                                             dL_dimage, dL_dmeans2d, dL_dconics, dL_dopacities,
+                                             dL_drgb, out_live, stats, ws, (hipStream_t)stream),
+                      "gs_raster_bwd");
+}
+
+int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const float* means3d,
+                      const float* scales, const float* quats, const float* opacities,
+                      const float* sh, const float* dL_dmeans2d, const float* dL_dconics,
+                      const float* dL_drgb, const float* dL_dopacities2d, float* dL_dmeans3d,
+                      float* dL_dscales, float* dL_dquats, float* dL_dopacities, float* dL_dsh,
+                      void* stream) {
+    GSR_TRY(check_cam(cam));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    if (n == 0) return ok();
+    GSR_NEED(means3d); GSR_NEED(scales); GSR_NEED(quats); GSR_NEED(opacities); GSR_NEED(sh);
+    GSR_NEED(dL_dmeans2d); GSR_NEED(dL_dconics); GSR_NEED(dL_drgb); GSR_NEED(dL_dopacities2d);
+    GSR_NEED(dL_dmeans3d); GSR_NEED(dL_dscales); GSR_NEED(dL_dquats); GSR_NEED(dL_dopacities);
+    GSR_NEED(dL_dsh);
+    const gsr::CamDev cd = gsr::make_cam(*cam);
+    return hip_status(gsr::launch_preprocess_bwd(cd, *cfg, n, means3d, scales, quats, opacities, sh,
+                                                 dL_dmeans2d, dL_dconics, dL_drgb, dL_dopacities2d,
+                                                 dL_dmeans3d, dL_dscales, dL_dquats, dL_dopacities,
+                                                 dL_dsh, (hipStream_t)stream),
+                      "gs_preprocess_bwd");
+}
+
+}  // extern "C"

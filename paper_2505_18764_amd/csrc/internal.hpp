@@ -1,0 +1,78 @@
+// internal.hpp -- host-side launcher declarations shared by the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gsr.h"
+
+namespace gsr {
+
+// Camera in the form the kernels take by value.
+struct CamDev {
+    float R[9];      // world->camera rotation, row-major
+    float t[3];
+    float campos[3]; // -R^T t
+    float fx, fy, cx, cy;
+    int width, height;
+    float znear;
+};
+
+CamDev make_cam(const gs_camera& c);
+
+// ---- layout of the raster workspace -------------------------------------------------------
+constexpr int TILE = 32;              // pixels per side of the tile one workgroup owns
+constexpr int REC_BYTES = 48;         // one staged splat record
+constexpr int GRAD_STRIDE = 16;       // floats per splat in the gradient accumulation buffer
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct RasterWs {
+    void* rec;         // [n] records in sorted order
+    void* rect;        // [n] uint2 tile rectangles
+    float* grad;       // [n * GRAD_STRIDE] (backward only)
+    unsigned long long* counters;  // [16] stats scratch
+};
+size_t raster_ws_bytes(int n, bool bwd);
+RasterWs carve_raster_ws(void* ws, int n, bool bwd);
+
+size_t sort_ws_bytes(int n, int key_bytes);
+size_t compact_ws_bytes(int n);
+
+// ---- launchers (return hipError_t of the last launch) -------------------------------------
+hipError_t launch_preprocess(const CamDev& cam, const gs_config& cfg, int n, const float* means3d,
+                             const float* scales, const float* quats, const float* opac,
+                             const float* sh, float* means2d, float* conics, float* rgb,
+                             float* depth, uint32_t* keys, int32_t* ids, int32_t* n_visible,
+                             void* ws, hipStream_t s);
+hipError_t launch_preprocess_bwd(const CamDev& cam, const gs_config& cfg, int n,
+                                 const float* means3d, const float* scales, const float* quats,
+                                 const float* opac, const float* sh, const float* g_means2d,
+                                 const float* g_conics, const float* g_rgb, const float* g_opac2d,
+                                 float* d_means3d, float* d_scales, float* d_quats, float* d_opac,
+                                 float* d_sh, hipStream_t s);
+hipError_t launch_prepare_2d(int width, int height, const gs_config& cfg, int n,
+                             const float* means2d, const float* conics, const float* opac,
+                             const float* depth, uint32_t* keys, int32_t* ids, int32_t* n_visible,
+                             void* ws, hipStream_t s);
+hipError_t launch_sort_u32(int n, uint32_t* keys, int32_t* vals, const int32_t* n_dev, void* ws,
+                           hipStream_t s);
+hipError_t launch_sort_u64(int n, uint64_t* keys, int32_t* vals, const int32_t* n_dev,
+                           int end_bit, void* ws, hipStream_t s);
+hipError_t launch_fill_u32(void* p, size_t count, uint32_t value, hipStream_t s);
+hipError_t launch_compact(int n, const uint32_t* key_by_id, uint32_t* keys, int32_t* ids,
+                          int32_t* n_visible, void* ws, hipStream_t s);
+hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
+                             const int32_t* sorted_ids, const int32_t* n_visible,
+                             const float* means2d, const float* conics, const float* opac,
+                             const float* rgb, void* fb, float* out_rgb, float* out_T,
+                             int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s);
+hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
+                             const int32_t* sorted_ids, const int32_t* n_visible,
+                             const float* means2d, const float* conics, const float* opac,
+                             const float* rgb, const void* fb, const float* dL_dimg,
+                             float* g_means2d, float* g_conics, float* g_opac, float* g_rgb,
+                             int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s);
+
+}  // namespace gsr

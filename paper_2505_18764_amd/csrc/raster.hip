@@ -1,0 +1,642 @@
+// raster.hip -- ordered splat compositing into a fixed-size per-pixel framebuffer (Eq. 2) and
+// the front-to-back gradient procedure with quad/wave gradient reduction (Sec. 3.1-3.2,
+// Procedures 1 and 2).
+//
+// Design (gfx950, wave64). CDNA has no rasterizer, no blend unit and no fragment interlock, so
+// the ordering that programmable blending gives the paper (Sec. 3.1.1) comes from ownership:
+//   * one workgroup (4 waves) owns a 32x32-pixel screen tile; each wave owns a 16x16 quadrant
+//     made of four 8x8 sub-blocks; lane l holds the same position in each sub-block, and lanes
+//     4k..4k+3 form a 2x2 pixel quad, so DPP quad_perm is the paper's quad;
+//   * the workgroup walks the globally depth-sorted splat array in order (no per-tile lists,
+//     memory O(N + pixels)): each fill, its waves test 4096 consecutive splats' tile rectangles,
+//     compact the hits in order into LDS, stage their records in LDS, and then every wave applies
+//     the staged splats one after another to its own pixels, whose state lives in VGPRs. A pixel
+//     is only ever touched by one lane, in splat order, so no interlock is needed;
+//   * a splat is skipped for a sub-block its pixel bounding box misses (one scalar branch).
+// Each fill iteration therefore processes one splat per wave across up to 64 lanes; that is the
+// "subgroup" of Procedure 2, and its live lanes always share one splat id (cohesion 100 %).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace gsr {
+
+constexpr int NT = 256;            // threads per workgroup
+constexpr int SPAN = 1024;         // sorted splats one wave tests per fill
+constexpr int CHUNK = 4 * SPAN;    // sorted splats the workgroup tests per fill
+constexpr int BATCH = 256;         // splat records staged in LDS at once
+
+// A staged splat: a = (mean x, mean y, conic a, conic b); b = (conic c, opacity, r, g);
+// c = (bits of colour b, sorted position, x0 | x1 << 16, y0 | y1 << 16) with the pixel bounding
+// box [x0, x1) x [y0, y1) of the alpha >= alpha_min ellipse, clamped to the image.
+struct __align__(16) Rec {
+    float4 a;
+    float4 b;
+    uint4 c;
+};
+static_assert(sizeof(Rec) == REC_BYTES, "record size");
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run of
+// tiles so that the splat records two neighbouring tiles share meet in one L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks, int ntiles) {
+    const int per = nblocks / 8;   // nblocks is a multiple of 8
+    return (bid % 8) * per + bid / 8;
+}
+
+__device__ __forceinline__ bool rect_hit(uint2 r, uint32_t tx, uint32_t ty) {
+    return (r.x & 0xFFFFu) <= tx && tx <= (r.x >> 16) && (r.y & 0xFFFFu) <= ty && ty <= (r.y >> 16);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---- setup: records and tile rectangles in sorted order --------------------------------------
+__global__ __launch_bounds__(256) void k_raster_setup(
+    int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
+    const float* __restrict__ means2d, const float* __restrict__ conics,
+    const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
+    int saturate, Rec* __restrict__ rec, uint2* __restrict__ rect) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int nvis = *nvis_ptr;
+    nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
+    uint2 rr = make_uint2(0xFFFFu, 0u);   // matches no tile
+    if (p < nvis) {
+        const int id = sorted_ids[p];
+        if ((unsigned)id < (unsigned)n) {
+            const float mx = means2d[2 * (size_t)id], my = means2d[2 * (size_t)id + 1];
+            const float a = conics[3 * (size_t)id], b = conics[3 * (size_t)id + 1],
+                        c = conics[3 * (size_t)id + 2];
+            const float o = opac[id];
+            float cr = rgb[3 * (size_t)id], cg = rgb[3 * (size_t)id + 1], cb = rgb[3 * (size_t)id + 2];
+            if (saturate) { cr = fminf(cr, 1.f); cg = fminf(cg, 1.f); cb = fminf(cb, 1.f); }
+            const float det = a * c - b * b;
+            if (a > 0.f && c > 0.f && det > 0.f && o >= amin && isfinite(mx) && isfinite(my)) {
+                // alpha >= alpha_min  <=>  q <= r2 = 2 ln(o / alpha_min): the ellipse's half
+                // extents are sqrt(r2 Sigma_xx), sqrt(r2 Sigma_yy) with Sigma = conic^-1;
+                // padded so FP32 rounding never puts a passing pixel outside the box.
+                const float r2 = 2.0f * logf(o / amin);
+                const float hx = sqrtf(fmaxf(r2 * c / det, 0.f)) * 1.001f + 0.01f;
+                const float hy = sqrtf(fmaxf(r2 * a / det, 0.f)) * 1.001f + 0.01f;
+                const float lim = 32768.f;
+                const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
+                const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), fminf((float)W, lim));
+                const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
+                const float fy1 = fminf(fmaxf(floorf(my + hy - 0.5f) + 1.f, 0.f), fminf((float)H, lim));
+                if (fx0 < fx1 && fy0 < fy1) {
+                    const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
+                    const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
+                    Rec r;
+                    r.a = make_float4(mx, my, a, b);
+                    r.b = make_float4(c, o, cr, cg);
+                    r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, x0 | (x1 << 16), y0 | (y1 << 16));
+                    rec[p] = r;
+                    rr = make_uint2((x0 / TILE) | (((x1 - 1) / TILE) << 16),
+                                    (y0 / TILE) | (((y1 - 1) / TILE) << 16));
+                }
+            }
+        }
+    }
+    rect[p] = rr;
+}
+
+// ---- the shared walk: scan 4096 sorted splats, compact hits in order, stage records ----------
+struct Walk {
+    uint16_t seg[4][SPAN];
+    int segn[4];
+    int alive[4];
+    Rec rec[BATCH];
+};
+
+// Tests the wave's 1024 splats of this fill against the tile; writes the in-order offsets of the
+// hits to w.seg[wave] and their count to w.segn[wave].
+__device__ __forceinline__ void scan_span(Walk& w, const uint2* __restrict__ rect, int wb, int nvis,
+                                          uint32_t ttx, uint32_t tty, int wave, int lane,
+                                          uint64_t lt) {
+    int cnt = 0;
+    if (wb < nvis) {
+        const int lim = min(SPAN, nvis - wb);
+#pragma unroll 4
+        for (int it0 = 0; it0 < SPAN / 64; it0 += 4) {
+            uint2 r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int o = (it0 + u) * 64 + lane;
+                r[u] = o < lim ? rect[wb + o] : make_uint2(0xFFFFu, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool hit = rect_hit(r[u], ttx, tty);
+                const uint64_t m = ballot(hit);
+                if (hit) w.seg[wave][cnt + popc(m & lt)] = (uint16_t)((it0 + u) * 64 + lane);
+                cnt += popc(m);
+            }
+        }
+    }
+    if (lane == 0) w.segn[wave] = cnt;
+}
+
+// Stages hits [b0, b0 + BATCH) of the fill (in order across the four waves' segments).
+__device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int base, int b0,
+                                      int total, int tid) {
+    const int e = b0 + tid;
+    if (e < total) {
+        int off = e, ws = 0;
+        if (off >= w.segn[0]) {
+            off -= w.segn[0]; ws = 1;
+            if (off >= w.segn[1]) {
+                off -= w.segn[1]; ws = 2;
+                if (off >= w.segn[2]) { off -= w.segn[2]; ws = 3; }
+            }
+        }
+        w.rec[tid] = rec[base + ws * SPAN + w.seg[ws][off]];
+    }
+}
+
+// ---- forward -------------------------------------------------------------------------------
+template <int RFMT, bool TCULL, bool INSTR>
+__global__ __launch_bounds__(NT) void k_raster_fwd(
+    int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
+    const uint2* __restrict__ rect, int W, int H, int tiles_x, int ntiles, float amin, float amax,
+    float tmin, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
+    float* __restrict__ out_T, int32_t* __restrict__ out_cov,
+    unsigned long long* __restrict__ stats) {
+    __shared__ Walk w;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+    if (tile >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = uniform(tid >> 6);
+    const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
+    const int wx0 = (int)ttx * TILE + (wave & 1) * 16, wy0 = (int)tty * TILE + (wave >> 1) * 16;
+    const int qd = lane >> 2;
+    const int lx = ((qd & 3) << 1) | (lane & 1), ly = ((qd >> 2) << 1) | ((lane >> 1) & 1);
+    const uint64_t lt = mask_lt(lane);
+
+    float px[4], py[4], C[4][3], T[4];
+    bool valid[4];
+    uint32_t nev[4], ncov[4];
+    uint32_t alive = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int X = wx0 + (s & 1) * 8 + lx, Y = wy0 + (s >> 1) * 8 + ly;
+        valid[s] = X < W && Y < H;
+        px[s] = (float)X + 0.5f;
+        py[s] = (float)Y + 0.5f;
+        C[s][0] = C[s][1] = C[s][2] = 0.f;
+        T[s] = 1.f;
+        nev[s] = ncov[s] = 0;
+        if (ballot(valid[s])) alive |= 1u << s;
+    }
+    int nvis = *nvis_ptr;
+    nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
+    uint32_t nq = 0;
+
+    for (int base = 0; base < nvis; base += CHUNK) {
+        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt);
+        __syncthreads();
+        const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
+        if (INSTR) nq += total;
+        bool stop = false;
+        for (int b0 = 0; b0 < total; b0 += BATCH) {
+            stage(w, rec, base, b0, total, tid);
+            __syncthreads();
+            const int m = min(BATCH, total - b0);
+            if (!TCULL || alive) {
+                for (int k = 0; k < m; ++k) {
+                    const float4 A = w.rec[k].a;
+                    const float4 B = w.rec[k].b;
+                    const uint4 Cw = w.rec[k].c;
+                    const uint32_t bx = uniform(Cw.z), by = uniform(Cw.w);
+                    const int x0 = bx & 0xFFFF, x1 = bx >> 16, y0 = by & 0xFFFF, y1 = by >> 16;
+                    const float cb = __uint_as_float(Cw.x);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int sx = wx0 + (s & 1) * 8, sy = wy0 + (s >> 1) * 8;
+                        if (x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy &&
+                            (!TCULL || ((alive >> s) & 1u))) {
+                            const float dx = px[s] - A.x, dy = py[s] - A.y;
+                            const float q = dx * fmaf(A.z, dx, 2.f * A.w * dy) + B.x * dy * dy;
+                            const float al = fminf(amax, B.y * __expf(-0.5f * q));
+                            bool pass = al >= amin;
+                            if (TCULL) pass = pass && T[s] >= tmin;
+                            if (pass) {
+                                const float wt = al * T[s];
+                                C[s][0] = fmaf(wt, B.z, C[s][0]);
+                                C[s][1] = fmaf(wt, B.w, C[s][1]);
+                                C[s][2] = fmaf(wt, cb, C[s][2]);
+                                T[s] = T[s] * (1.f - al);
+                                if constexpr (RFMT >= 0) {
+                                    C[s][0] = fb_round<RFMT>(C[s][0]);
+                                    C[s][1] = fb_round<RFMT>(C[s][1]);
+                                    C[s][2] = fb_round<RFMT>(C[s][2]);
+                                    T[s] = fb_round<RFMT>(T[s]);
+                                }
+                            }
+                            if (INSTR) {
+                                nev[s] += valid[s];
+                                ncov[s] += (pass && valid[s]);
+                            }
+                            if (TCULL && !ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
+                        }
+                    }
+                }
+            }
+            if (TCULL && lane == 0) w.alive[wave] = (int)alive;
+            __syncthreads();
+            if (TCULL && !(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3])) { stop = true; break; }
+        }
+        if (TCULL && stop) break;
+    }
+
+    const size_t P = (size_t)W * H;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (!valid[s]) continue;
+        const int X = wx0 + (s & 1) * 8 + lx, Y = wy0 + (s >> 1) * 8 + ly;
+        const size_t i = (size_t)Y * W + X;
+        float4 v = make_float4(C[s][0], C[s][1], C[s][2], T[s]);
+        fb_store(fb, fb_fmt, i, v);
+        if (out_rgb) {
+            out_rgb[i] = v.x;
+            out_rgb[P + i] = v.y;
+            out_rgb[2 * P + i] = v.z;
+        }
+        if (out_T) out_T[i] = v.w;
+        if (INSTR && out_cov) out_cov[i] = (int32_t)ncov[s];
+    }
+    if (INSTR && stats) {
+        uint32_t e = nev[0] + nev[1] + nev[2] + nev[3];
+        uint32_t c = ncov[0] + ncov[1] + ncov[2] + ncov[3];
+        e = wave_sum_u32(e);
+        c = wave_sum_u32(c);
+        if (lane == 0) {
+            if (wave == 0) atomicAdd(&stats[0], (unsigned long long)nq);
+            atomicAdd(&stats[1], (unsigned long long)e);
+            atomicAdd(&stats[2], (unsigned long long)c);
+        }
+    }
+}
+
+// ---- backward ------------------------------------------------------------------------------
+
+struct BwdCounts {
+    uint32_t evaluated, live, sets, wave_red, quad_red, cohesive;
+};
+
+// Procedure 2 (ReduceGradient) for one splat and one wave: `g` holds this lane's gradient
+// contribution (zero when not live); `gp` is the splat's slot in the accumulation buffer.
+template <bool INSTR>
+__device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* __restrict__ gp,
+                                              int mode, int X, int lane, BwdCounts& cnt) {
+    const uint64_t m = ballot(live);
+    if (m == 0) return;
+    const int nl = popc(m);
+    if (mode == GS_REDUCE_NAIVE) {
+        if (live)
+#pragma unroll
+            for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, g[j]);
+        if (INSTR && lane == 0) cnt.sets += nl;
+        return;
+    }
+    // All live lanes of the wave hold the same splat (one splat per wave iteration), so
+    // subgroupAllEqual(i) holds; the wave path needs only the live-lane threshold X.
+    if (mode != GS_REDUCE_QUAD && nl >= X) {
+        float tot[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) tot[j] = wave_sum(g[j]);
+        if (lane == __builtin_ctzll(m))          // subgroupBallotFindLSB(reduceMask)
+#pragma unroll
+            for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, tot[j]);
+        if (INSTR && lane == 0) { cnt.sets += 1; cnt.wave_red += 1; cnt.cohesive += 1; }
+        return;
+    }
+    if (mode == GS_REDUCE_WAVE) {                // standalone subgroup reduction: no quad path
+        if (live)
+#pragma unroll
+            for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, g[j]);
+        if (INSTR && lane == 0) cnt.sets += nl;
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) g[j] = quad_sum(g[j]);
+    const uint32_t qm = (uint32_t)(m >> (lane & ~3)) & 0xFu;   // reduceMask restricted to the quad
+    const bool leader = qm != 0u && (uint32_t)(lane & 3) == (uint32_t)__builtin_ctz(qm | 0x10u);
+    if (leader)
+#pragma unroll
+        for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, g[j]);
+    if (INSTR) {
+        const uint64_t lm = ballot(leader);
+        if (lane == 0) { cnt.sets += popc(lm); cnt.quad_red += 1; cnt.cohesive += 1; }
+    }
+}
+
+template <int RFMT, bool INSTR>
+__global__ __launch_bounds__(NT) void k_raster_bwd(
+    int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
+    const uint2* __restrict__ rect, int W, int H, int tiles_x, int ntiles, float amin, float amax,
+    float tmin, int fb_fmt, const void* __restrict__ fb, const float* __restrict__ dL_dimg,
+    int mode, int X, float* __restrict__ grad, int32_t* __restrict__ out_live,
+    unsigned long long* __restrict__ stats) {
+    __shared__ Walk w;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles);
+    if (tile >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = uniform(tid >> 6);
+    const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
+    const int wx0 = (int)ttx * TILE + (wave & 1) * 16, wy0 = (int)tty * TILE + (wave >> 1) * 16;
+    const int qd = lane >> 2;
+    const int lx = ((qd & 3) << 1) | (lane & 1), ly = ((qd >> 2) << 1) | ((lane >> 1) & 1);
+    const uint64_t lt = mask_lt(lane);
+    const size_t P = (size_t)W * H;
+
+    // Procedure 1's per-pixel state (C', T), initialised to (C, 1) from the framebuffer, and the
+    // read-only dL/dC.
+    float px[4], py[4], Cp[4][3], T[4], G[4][3];
+    bool valid[4];
+    uint32_t nlive[4];
+    uint32_t alive = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int X = wx0 + (s & 1) * 8 + lx, Y = wy0 + (s >> 1) * 8 + ly;
+        valid[s] = X < W && Y < H;
+        px[s] = (float)X + 0.5f;
+        py[s] = (float)Y + 0.5f;
+        T[s] = 1.f;
+        nlive[s] = 0;
+        Cp[s][0] = Cp[s][1] = Cp[s][2] = 0.f;
+        G[s][0] = G[s][1] = G[s][2] = 0.f;
+        if (valid[s]) {
+            const size_t i = (size_t)Y * W + X;
+            const float4 v = fb_load(fb, fb_fmt, i);
+            Cp[s][0] = v.x; Cp[s][1] = v.y; Cp[s][2] = v.z;
+            G[s][0] = dL_dimg[i]; G[s][1] = dL_dimg[P + i]; G[s][2] = dL_dimg[2 * P + i];
+        }
+        if (ballot(valid[s])) alive |= 1u << s;
+    }
+    int nvis = *nvis_ptr;
+    nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
+    BwdCounts cnt = {0, 0, 0, 0, 0, 0};
+    uint32_t nq = 0;
+    const bool lane_acc = (mode == GS_REDUCE_HYBRID_LANE);
+
+    for (int base = 0; base < nvis; base += CHUNK) {
+        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt);
+        __syncthreads();
+        const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
+        if (INSTR) nq += total;
+        bool stop = false;
+        for (int b0 = 0; b0 < total; b0 += BATCH) {
+            stage(w, rec, base, b0, total, tid);
+            __syncthreads();
+            const int m = min(BATCH, total - b0);
+            for (int k = 0; k < m && alive; ++k) {
+                const float4 A = w.rec[k].a;
+                const float4 B = w.rec[k].b;
+                const uint4 Cw = w.rec[k].c;
+                const uint32_t bx = uniform(Cw.z), by = uniform(Cw.w);
+                const int x0 = bx & 0xFFFF, x1 = bx >> 16, y0 = by & 0xFFFF, y1 = by >> 16;
+                const float cr = B.z, cg = B.w, cb = __uint_as_float(Cw.x);
+                float* gp = grad + (size_t)uniform(Cw.y) * GRAD_STRIDE;
+                float acc[9];
+#pragma unroll
+                for (int j = 0; j < 9; ++j) acc[j] = 0.f;
+                bool acc_live = false;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int sx = wx0 + (s & 1) * 8, sy = wy0 + (s >> 1) * 8;
+                    if (!(x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy && ((alive >> s) & 1u)))
+                        continue;
+                    const float dx = px[s] - A.x, dy = py[s] - A.y;
+                    const float q = dx * fmaf(A.z, dx, 2.f * A.w * dy) + B.x * dy * dy;
+                    const float e = __expf(-0.5f * q);
+                    const float araw = B.y * e;
+                    const float al = fminf(amax, araw);
+                    // cullingFlag: splat boundary (alpha < 1/255), then T-Culling (T < 1e-4)
+                    const bool live = valid[s] && al >= amin && T[s] >= tmin;
+                    float g[9];
+#pragma unroll
+                    for (int j = 0; j < 9; ++j) g[j] = 0.f;
+                    if (live) {
+                        const float Ti = T[s];
+                        const float wt = al * Ti;
+                        // Eq. 3: dL/dc = dL/dC alpha T
+                        g[6] = G[s][0] * wt;
+                        g[7] = G[s][1] * wt;
+                        g[8] = G[s][2] * wt;
+                        // Eq. 7: dL/dalpha = dL/dC . (c T - C') / (1 - alpha)
+                        const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) + G[s][1] * (cg * Ti - Cp[s][1]) +
+                                          G[s][2] * (cb * Ti - Cp[s][2])) *
+                                         __builtin_amdgcn_rcpf(1.f - al);
+                        // Eqs. 5, 6: the state update, stored back
+                        Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
+                        Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
+                        Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
+                        T[s] = Ti * (1.f - al);
+                        if constexpr (RFMT >= 0) {
+                            Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
+                            Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
+                            Cp[s][2] = fb_round<RFMT>(Cp[s][2]);
+                            T[s] = fb_round<RFMT>(T[s]);
+                        }
+                        // bwd_diff: alpha = o exp(-q/2) (zero gradient where clamped)
+                        if (araw < amax) {
+                            const float gq = -0.5f * ga * araw;
+                            g[5] = ga * e;
+                            g[0] = -2.f * gq * fmaf(A.z, dx, A.w * dy);
+                            g[1] = -2.f * gq * fmaf(A.w, dx, B.x * dy);
+                            g[2] = gq * dx * dx;
+                            g[3] = 2.f * gq * dx * dy;
+                            g[4] = gq * dy * dy;
+                        }
+                    }
+                    if (INSTR) {
+                        cnt.evaluated += valid[s];
+                        cnt.live += live;
+                        nlive[s] += live;
+                    }
+                    if (lane_acc) {
+#pragma unroll
+                        for (int j = 0; j < 9; ++j) acc[j] += g[j];
+                        acc_live = acc_live || live;
+                    } else {
+                        reduce_commit<INSTR>(g, live, gp, mode, X, lane, cnt);
+                    }
+                    if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
+                }
+                if (lane_acc) reduce_commit<INSTR>(acc, acc_live, gp, GS_REDUCE_HYBRID, X, lane, cnt);
+            }
+            if (lane == 0) w.alive[wave] = (int)alive;
+            __syncthreads();
+            if (!(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3])) { stop = true; break; }
+        }
+        if (stop) break;
+    }
+
+    if (INSTR && out_live) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (!valid[s]) continue;
+            const int X = wx0 + (s & 1) * 8 + lx, Y = wy0 + (s >> 1) * 8 + ly;
+            out_live[(size_t)Y * W + X] = (int32_t)nlive[s];
+        }
+    }
+    if (INSTR && stats) {
+        const uint32_t e = wave_sum_u32(cnt.evaluated), l = wave_sum_u32(cnt.live);
+        if (lane == 0) {
+            if (wave == 0) atomicAdd(&stats[3], (unsigned long long)nq);
+            atomicAdd(&stats[4], (unsigned long long)e);
+            atomicAdd(&stats[5], (unsigned long long)l);
+            atomicAdd(&stats[6], (unsigned long long)cnt.sets);
+            atomicAdd(&stats[7], (unsigned long long)cnt.wave_red);
+            atomicAdd(&stats[8], (unsigned long long)cnt.quad_red);
+            atomicAdd(&stats[9], (unsigned long long)cnt.cohesive);
+        }
+    }
+}
+
+// Scatter the accumulated gradients from sorted position to splat id; zero for culled splats.
+__global__ __launch_bounds__(256) void k_grad_finalize(
+    int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
+    const float* __restrict__ grad, const float* __restrict__ rgb, int saturate,
+    float* __restrict__ g_m, float* __restrict__ g_c, float* __restrict__ g_o,
+    float* __restrict__ g_rgb) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int nvis = *nvis_ptr;
+    nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
+    const int id = sorted_ids[p];
+    if ((unsigned)id >= (unsigned)n) return;
+    float v[9];
+    if (p < nvis) {
+        const float4* gp = reinterpret_cast<const float4*>(grad + (size_t)p * GRAD_STRIDE);
+        const float4 u0 = gp[0], u1 = gp[1];
+        const float u2 = grad[(size_t)p * GRAD_STRIDE + 8];
+        v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+        v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w; v[8] = u2;
+        if (saturate)
+            for (int ch = 0; ch < 3; ++ch)
+                if (rgb[3 * (size_t)id + ch] > 1.f) v[6 + ch] = 0.f;
+    } else {
+        for (int j = 0; j < 9; ++j) v[j] = 0.f;
+    }
+    g_m[2 * (size_t)id] = v[0];
+    g_m[2 * (size_t)id + 1] = v[1];
+    g_c[3 * (size_t)id] = v[2];
+    g_c[3 * (size_t)id + 1] = v[3];
+    g_c[3 * (size_t)id + 2] = v[4];
+    g_o[id] = v[5];
+    g_rgb[3 * (size_t)id] = v[6];
+    g_rgb[3 * (size_t)id + 1] = v[7];
+    g_rgb[3 * (size_t)id + 2] = v[8];
+}
+
+// ---- host side -------------------------------------------------------------------------------
+
+size_t raster_ws_bytes(int n, bool bwd) {
+    size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up(16 * 8);
+    if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4);
+    return b;
+}
+
+RasterWs carve_raster_ws(void* ws, int n, bool bwd) {
+    RasterWs r;
+    char* p = (char*)ws;
+    r.rec = p;      p += align_up((size_t)n * REC_BYTES);
+    r.rect = p;     p += align_up((size_t)n * 8);
+    r.counters = (unsigned long long*)p; p += align_up(16 * 8);
+    r.grad = bwd ? (float*)p : nullptr;
+    return r;
+}
+
+static bool saturating(int fmt) { return fmt == FB_UNORM16 || fmt == FB_UNORM8; }
+
+template <bool TC, bool IN>
+static void fwd_by_fmt(int rfmt, void (*&k)(int, const int32_t*, const Rec*, const uint2*, int, int,
+                                             int, int, float, float, float, int, void*, float*,
+                                             float*, int32_t*, unsigned long long*)) {
+    switch (rfmt) {
+    case FB_F32: k = k_raster_fwd<FB_F32, TC, IN>; break;
+    case FB_F16: k = k_raster_fwd<FB_F16, TC, IN>; break;
+    case FB_UNORM16: k = k_raster_fwd<FB_UNORM16, TC, IN>; break;
+    case FB_BF16: k = k_raster_fwd<FB_BF16, TC, IN>; break;
+    case FB_UNORM8: k = k_raster_fwd<FB_UNORM8, TC, IN>; break;
+    default: k = k_raster_fwd<-1, TC, IN>; break;
+    }
+}
+
+hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
+                             const int32_t* sorted_ids, const int32_t* n_visible,
+                             const float* means2d, const float* conics, const float* opac,
+                             const float* rgb, void* fb, float* out_rgb, float* out_T,
+                             int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s) {
+    const RasterWs r = carve_raster_ws(ws, n, false);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_raster_setup, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
+                           n_visible, means2d, conics, opac, rgb, width, height, cfg.alpha_min,
+                           (int)saturating(cfg.fb_format), (Rec*)r.rec, (uint2*)r.rect);
+    }
+    const int tiles_x = (width + TILE - 1) / TILE, tiles_y = (height + TILE - 1) / TILE;
+    const int ntiles = tiles_x * tiles_y;
+    const int nblocks = (ntiles + 7) / 8 * 8;
+    const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
+    const bool tcull = cfg.t_min_fwd > 0.f;
+    const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_cov;
+    void (*k)(int, const int32_t*, const Rec*, const uint2*, int, int, int, int, float, float, float,
+              int, void*, float*, float*, int32_t*, unsigned long long*) = nullptr;
+    if (tcull) { if (instr) fwd_by_fmt<true, true>(rfmt, k); else fwd_by_fmt<true, false>(rfmt, k); }
+    else { if (instr) fwd_by_fmt<false, true>(rfmt, k); else fwd_by_fmt<false, false>(rfmt, k); }
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
+                       (const uint2*)r.rect, width, height, tiles_x, ntiles, cfg.alpha_min,
+                       cfg.alpha_max, cfg.t_min_fwd, cfg.fb_format, fb, out_rgb, out_T, out_cov,
+                       (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
+                             const int32_t* sorted_ids, const int32_t* n_visible,
+                             const float* means2d, const float* conics, const float* opac,
+                             const float* rgb, const void* fb, const float* dL_dimg,
+                             float* g_means2d, float* g_conics, float* g_opac, float* g_rgb,
+                             int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s) {
+    const RasterWs r = carve_raster_ws(ws, n, true);
+    const int sat = (int)saturating(cfg.fb_format);
+    if (n > 0) {
+        hipError_t e = launch_fill_u32(r.grad, (size_t)n * GRAD_STRIDE, 0u, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_raster_setup, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
+                           n_visible, means2d, conics, opac, rgb, width, height, cfg.alpha_min,
+                           sat, (Rec*)r.rec, (uint2*)r.rect);
+    }
+    const int tiles_x = (width + TILE - 1) / TILE, tiles_y = (height + TILE - 1) / TILE;
+    const int ntiles = tiles_x * tiles_y;
+    const int nblocks = (ntiles + 7) / 8 * 8;
+    const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
+    const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_live;
+    void (*k)(int, const int32_t*, const Rec*, const uint2*, int, int, int, int, float, float, float,
+              int, const void*, const float*, int, int, float*, int32_t*, unsigned long long*) =
+        nullptr;
+#define GSR_BWD_PICK(IN)                                             \
+    switch (rfmt) {                                                  \
+    case FB_F32: k = k_raster_bwd<FB_F32, IN>; break;                \
+    case FB_F16: k = k_raster_bwd<FB_F16, IN>; break;                \
+    case FB_UNORM16: k = k_raster_bwd<FB_UNORM16, IN>; break;        \
+    case FB_BF16: k = k_raster_bwd<FB_BF16, IN>; break;              \
+    case FB_UNORM8: k = k_raster_bwd<FB_UNORM8, IN>; break;          \
+    default: k = k_raster_bwd<-1, IN>; break;                        \
+    }
+    if (instr) { GSR_BWD_PICK(true) } else { GSR_BWD_PICK(false) }
+#undef GSR_BWD_PICK
+    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
+                       (const uint2*)r.rect, width, height, tiles_x, ntiles, cfg.alpha_min,
+                       cfg.alpha_max, cfg.t_min_bwd, cfg.fb_format, fb, dL_dimg, cfg.reduce_mode,
+                       cfg.reduce_threshold, r.grad, out_live,
+                       (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
+                       n_visible, r.grad, rgb, sat, g_means2d, g_conics, g_opac, g_rgb);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

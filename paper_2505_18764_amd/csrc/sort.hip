@@ -1,0 +1,309 @@
+// sort.hip -- stable LSD radix sort of (key, int32 value) pairs with the sort length read on
+// the device (the depth sort of Sec. 1 and Sec. 4.1, dynamic length after frustum culling).
+//
+// Each 8-bit digit pass: (1) per-block digit histograms, (2) one exclusive scan over the
+// digit-major [digit][block] table, (3) a stable scatter in which every block ranks its keys
+// round by round (256 keys per round, one per thread, in input order), ranking equal digits
+// inside a wave with eight ballots and across the four waves through LDS counts.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace gsr {
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ROUNDS = 16;
+constexpr int SORT_ITEMS = SORT_THREADS * SORT_ROUNDS;   // keys per block
+constexpr int SCAN_ITEMS = 4096;                         // entries per scan block (256 x 16)
+
+__device__ __forceinline__ int dev_count(const int32_t* n_dev, int n_max) {
+    int n = n_dev ? *n_dev : n_max;
+    return n < 0 ? 0 : (n > n_max ? n_max : n);
+}
+
+template <typename K>
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const K* __restrict__ keys, int n_max,
+                                                            const int32_t* __restrict__ n_dev,
+                                                            int shift, int nblocks,
+                                                            uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int n = dev_count(n_dev, n_max);
+    const int start = blockIdx.x * SORT_ITEMS;
+    if (start < n) {
+        for (int r = 0; r < SORT_ROUNDS; ++r) {
+            const int idx = start + r * SORT_THREADS + tid;
+            if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 0xFFu], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
+}
+
+// Exclusive scan of `count` uint32 in three launches: block sums, scan of the sums, apply.
+__global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ in, size_t count,
+                                                   uint32_t* __restrict__ sums) {
+    __shared__ uint32_t red[4];
+    const size_t base = (size_t)blockIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS / 256; ++j) {
+        const size_t i = base + (size_t)j * 256 + threadIdx.x;
+        if (i < count) s += in[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Single block: exclusive scan of `count` (<= 1024 * 64) block sums in place.
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, int count) {
+    __shared__ uint32_t part[1024];
+    const int per = (count + 1023) / 1024;
+    const int lo = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int j = 0; j < per; ++j)
+        if (lo + j < count) s += sums[lo + j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {     // Hillis-Steele inclusive scan
+        uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+    for (int j = 0; j < per; ++j)
+        if (lo + j < count) {
+            const uint32_t v = sums[lo + j];
+            sums[lo + j] = run;
+            run += v;
+        }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, size_t count,
+                                                    const uint32_t* __restrict__ sums,
+                                                    uint32_t* __restrict__ out) {
+    // each thread owns 16 consecutive entries of the block's 4096
+    __shared__ uint32_t part[256];
+    const size_t base = (size_t)blockIdx.x * SCAN_ITEMS + (size_t)threadIdx.x * 16;
+    uint32_t v[16];
+    uint32_t s = 0;
+    for (int j = 0; j < 16; ++j) {
+        v[j] = (base + j < count) ? in[base + j] : 0u;
+        s += v[j];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t t = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = sums[blockIdx.x] + (threadIdx.x ? part[threadIdx.x - 1] : 0u);
+    for (int j = 0; j < 16; ++j)
+        if (base + j < count) {
+            out[base + j] = run;
+            run += v[j];
+        }
+}
+
+static hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, size_t count, uint32_t* sums,
+                                 hipStream_t s) {
+    const int blocks = (int)((count + SCAN_ITEMS - 1) / SCAN_ITEMS);
+    hipLaunchKernelGGL(k_scan_sums, dim3(blocks), dim3(256), 0, s, in, count, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, blocks);
+    hipLaunchKernelGGL(k_scan_apply, dim3(blocks), dim3(256), 0, s, in, count, sums, out);
+    return hipGetLastError();
+}
+
+template <typename K>
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
+    const K* __restrict__ kin, const int32_t* __restrict__ vin, K* __restrict__ kout,
+    int32_t* __restrict__ vout, int n_max, const int32_t* __restrict__ n_dev, int shift,
+    int nblocks, const uint32_t* __restrict__ offsets) {
+    __shared__ uint32_t s_off[256];
+    __shared__ uint16_t s_cnt[2][4][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = dev_count(n_dev, n_max);
+    const int start = blockIdx.x * SORT_ITEMS;
+    if (start >= n) return;                         // uniform for the block
+    s_off[tid] = offsets[(size_t)tid * nblocks + blockIdx.x];
+    for (int b = 0; b < 2; ++b)
+        for (int w = 0; w < 4; ++w) s_cnt[b][w][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = mask_lt(lane);
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int buf = r & 1;
+        const int idx = start + r * SORT_THREADS + tid;
+        const bool valid = idx < n;
+        K key = 0;
+        int32_t val = 0;
+        uint32_t d = 0;
+        if (valid) {
+            key = kin[idx];
+            val = vin[idx];
+            d = (uint32_t)(key >> shift) & 0xFFu;
+        }
+        // lanes of this wave with the same digit
+        uint64_t peers = ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = ballot(valid && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        if (!valid) peers = 0;
+        const int rank = popc(peers & lt);
+        if (valid && rank == 0) s_cnt[buf][wave][d] = (uint16_t)popc(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = s_off[d] + (uint32_t)rank;
+            for (int w = 0; w < wave; ++w) off += s_cnt[buf][w][d];
+            kout[off] = key;
+            vout[off] = val;
+        }
+        __syncthreads();
+        // thread `tid` owns digit `tid`: advance its offset and clear its column for round r+2
+        s_off[tid] += (uint32_t)s_cnt[buf][0][tid] + s_cnt[buf][1][tid] + s_cnt[buf][2][tid] +
+                      s_cnt[buf][3][tid];
+        for (int w = 0; w < 4; ++w) s_cnt[buf][w][tid] = 0;
+    }
+}
+
+template <typename K>
+__global__ void k_copy_pairs(const K* __restrict__ ks, const int32_t* __restrict__ vs,
+                             K* __restrict__ kd, int32_t* __restrict__ vd, int n_max,
+                             const int32_t* __restrict__ n_dev) {
+    const int n = dev_count(n_dev, n_max);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+// ---- order-preserving compaction of the visible splats (frustum culling, Sec. 4.1) -------
+// keys_by_id[i] == 0xFFFFFFFF marks a culled splat. Output: (keys, ids) with the visible splats
+// first in id order, then the culled ones in id order; n_visible = number of visible splats.
+
+__global__ __launch_bounds__(SORT_THREADS) void k_compact_count(const uint32_t* __restrict__ kid,
+                                                                int n, uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t red[4];
+    const int start = blockIdx.x * SORT_ITEMS;
+    uint32_t c = 0;
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int i = start + r * SORT_THREADS + threadIdx.x;
+        c += popc(ballot(i < n && kid[i] != 0xFFFFFFFFu)) * (lane_id() == 0);
+    }
+    if (lane_id() == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_compact_scatter(
+    const uint32_t* __restrict__ kid, int n, int nblocks, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ offs, uint32_t* __restrict__ keys, int32_t* __restrict__ ids,
+    int32_t* __restrict__ n_visible) {
+    __shared__ uint32_t s_w[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t total = offs[nblocks - 1] + cnt[nblocks - 1];
+    if (blockIdx.x == 0 && tid == 0) *n_visible = (int32_t)total;
+    const int start = blockIdx.x * SORT_ITEMS;
+    uint32_t vis_run = offs[blockIdx.x];
+    uint32_t cul_run = total + ((uint32_t)start - offs[blockIdx.x]);
+    const uint64_t lt = mask_lt(lane);
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int i = start + r * SORT_THREADS + tid;
+        const bool in = i < n;
+        const uint32_t k = in ? kid[i] : 0xFFFFFFFFu;
+        const bool v = in && k != 0xFFFFFFFFu;
+        const uint64_t mv = ballot(v), mc = ballot(in && !v);
+        if (lane == 0) { s_w[0][wave] = popc(mv); s_w[1][wave] = popc(mc); }
+        __syncthreads();
+        uint32_t pv = vis_run, pc = cul_run;
+        for (int w = 0; w < wave; ++w) { pv += s_w[0][w]; pc += s_w[1][w]; }
+        if (v) { keys[pv + popc(mv & lt)] = k; ids[pv + popc(mv & lt)] = i; }
+        else if (in) { keys[pc + popc(mc & lt)] = k; ids[pc + popc(mc & lt)] = i; }
+        vis_run += s_w[0][0] + s_w[0][1] + s_w[0][2] + s_w[0][3];
+        cul_run += s_w[1][0] + s_w[1][1] + s_w[1][2] + s_w[1][3];
+        __syncthreads();
+    }
+}
+
+size_t compact_ws_bytes(int n) {
+    const size_t nb = (size_t)((n + SORT_ITEMS - 1) / SORT_ITEMS + 1);
+    return align_up(nb * 4) * 2 + align_up(((nb + SCAN_ITEMS - 1) / SCAN_ITEMS) * 4);
+}
+
+hipError_t launch_compact(int n, const uint32_t* key_by_id, uint32_t* keys, int32_t* ids,
+                          int32_t* n_visible, void* ws, hipStream_t s) {
+    if (n == 0) return launch_fill_u32(n_visible, 1, 0u, s);
+    const int nb = (n + SORT_ITEMS - 1) / SORT_ITEMS;
+    char* p = (char*)ws;
+    uint32_t* cnt = (uint32_t*)p;  p += align_up((size_t)(nb + 1) * 4);
+    uint32_t* offs = (uint32_t*)p; p += align_up((size_t)(nb + 1) * 4);
+    uint32_t* sums = (uint32_t*)p;
+    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(SORT_THREADS), 0, s, key_by_id, n, cnt);
+    hipError_t e = exclusive_scan(cnt, offs, (size_t)nb, sums, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(SORT_THREADS), 0, s, key_by_id, n, nb,
+                       cnt, offs, keys, ids, n_visible);
+    return hipGetLastError();
+}
+
+static int sort_blocks(int n) { return (n + SORT_ITEMS - 1) / SORT_ITEMS; }
+
+size_t sort_ws_bytes(int n, int key_bytes) {
+    const size_t nb = (size_t)(n > 0 ? sort_blocks(n) : 1);
+    const size_t table = 256 * nb;
+    const size_t sums = (table + SCAN_ITEMS - 1) / SCAN_ITEMS;
+    return align_up((size_t)n * key_bytes) + align_up((size_t)n * 4) + align_up(table * 4) * 2 +
+           align_up(sums * 4);
+}
+
+template <typename K>
+static hipError_t sort_pairs(int n, K* keys, int32_t* vals, const int32_t* n_dev, int end_bit,
+                             void* ws, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int nb = sort_blocks(n);
+    const size_t table = 256 * (size_t)nb;
+    char* p = (char*)ws;
+    K* kalt = (K*)p;            p += align_up((size_t)n * sizeof(K));
+    int32_t* valt = (int32_t*)p; p += align_up((size_t)n * 4);
+    uint32_t* hist = (uint32_t*)p; p += align_up(table * 4);
+    uint32_t* offs = (uint32_t*)p; p += align_up(table * 4);
+    uint32_t* sums = (uint32_t*)p;
+    if ((table + SCAN_ITEMS - 1) / SCAN_ITEMS > 1024 * 64) return hipErrorInvalidValue;
+    K* kin = keys; int32_t* vin = vals;
+    K* kout = kalt; int32_t* vout = valt;
+    int passes = 0;
+    for (int shift = 0; shift < end_bit; shift += 8, ++passes) {
+        hipLaunchKernelGGL(k_sort_hist<K>, dim3(nb), dim3(SORT_THREADS), 0, s, kin, n, n_dev,
+                           shift, nb, hist);
+        hipError_t e = exclusive_scan(hist, offs, table, sums, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sort_scatter<K>, dim3(nb), dim3(SORT_THREADS), 0, s, kin, vin, kout,
+                           vout, n, n_dev, shift, nb, offs);
+        K* tk = kin; kin = kout; kout = tk;
+        int32_t* tv = vin; vin = vout; vout = tv;
+    }
+    if (passes & 1) {   // result sits in the alternate buffers: copy back
+        int blocks = (n + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_copy_pairs<K>, dim3(blocks), dim3(256), 0, s, kin, vin, keys, vals,
+                           n, n_dev);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_u32(int n, uint32_t* keys, int32_t* vals, const int32_t* n_dev, void* ws,
+                           hipStream_t s) {
+    return sort_pairs<uint32_t>(n, keys, vals, n_dev, 32, ws, s);
+}
+
+hipError_t launch_sort_u64(int n, uint64_t* keys, int32_t* vals, const int32_t* n_dev,
+                           int end_bit, void* ws, hipStream_t s) {
+    return sort_pairs<uint64_t>(n, keys, vals, n_dev, end_bit, ws, s);
+}
+
+}  // namespace gsr

@@ -1,0 +1,308 @@
+"""Torch-facing layer over the C ABI: configuration, workspaces, the five pipeline stages and the
+autograd Functions.
+
+PyTorch only supplies device memory and the current stream; every step of the method runs in the
+HIP library. The forward state kept for the backward is O(N) splat records plus the O(W H)
+framebuffer: nothing per fragment is stored, the backward rematerialises each fragment from the
+framebuffer state (Procedure 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _f32(x):
+    return float(np.float32(x))
+
+
+@dataclasses.dataclass
+class RasterConfig:
+    """Method constants and switches (mirrors gs_config). Defaults are the paper's: alpha_min
+    1/255, backward T-cull 1e-4, no forward T-cull, hybrid reduction with X = 8, FP32 state."""
+    fb_format: str = "f32"            # f32 | f16 | unorm16 | bf16 | unorm8
+    fb_round: str = "at_rest"         # at_rest | per_fragment
+    reduce_mode: str = "hybrid"       # naive | quad | wave | hybrid | hybrid_lane
+    reduce_threshold: int = 8
+    t_min_fwd: float = 0.0
+    t_min_bwd: float = _f32(1e-4)
+    alpha_min: float = _f32(1.0 / 255.0)
+    alpha_max: float = _f32(0.99)
+    eps2d: float = _f32(0.3)
+    sh_degree: int = 3
+    stats: bool = False
+
+    def c(self) -> L.GsConfig:
+        c = L.GsConfig()
+        c.alpha_min = self.alpha_min
+        c.alpha_max = self.alpha_max
+        c.t_min_fwd = self.t_min_fwd
+        c.t_min_bwd = self.t_min_bwd
+        c.eps2d = self.eps2d
+        c.sh_degree = self.sh_degree
+        c.fb_format = L.FB_FORMATS[self.fb_format]
+        c.fb_round = L.FB_ROUND[self.fb_round]
+        c.reduce_mode = L.REDUCE_MODES[self.reduce_mode]
+        c.reduce_threshold = self.reduce_threshold
+        c.flags = 1 if self.stats else 0
+        return c
+
+
+def camera_c(cam) -> L.GsCamera:
+    """gs_camera from any object with viewmat (3x4), fx, fy, cx, cy, width, height, znear."""
+    c = L.GsCamera()
+    vm = np.asarray(cam.viewmat, dtype=np.float32).reshape(-1)
+    for i in range(12):
+        c.viewmat[i] = float(vm[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.znear = float(getattr(cam, "znear", 0.2))
+    return c
+
+
+class _Size:
+    def __init__(self, width, height):
+        self.width, self.height = int(width), int(height)
+
+
+def image_camera(width, height) -> L.GsCamera:
+    """A camera that carries only the image size (for the 2D entry points)."""
+    c = L.GsCamera()
+    c.viewmat[0] = c.viewmat[5] = c.viewmat[10] = 1.0
+    c.fx = c.fy = 1.0
+    c.width, c.height, c.znear = int(width), int(height), 0.2
+    return c
+
+
+class Workspace:
+    """A growing device scratch buffer (256-byte aligned). Reused across calls on one stream;
+    its size only depends on (n, width, height, format), see gs_workspace_size."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf = None
+
+    def get(self, nbytes: int):
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    @property
+    def nbytes(self) -> int:
+        return 0 if self.buf is None else self.buf.numel()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ws_args(ws: Workspace, need: int):
+    b = ws.get(need)
+    return b, b.numel()
+
+
+@dataclasses.dataclass
+class Projected:
+    """Splats in screen space plus the depth-sorted (keys, ids) and the device-side count of
+    visible splats."""
+    means2d: torch.Tensor
+    conics: torch.Tensor
+    rgb: torch.Tensor
+    opacities: torch.Tensor
+    depth: torch.Tensor
+    keys: torch.Tensor
+    ids: torch.Tensor
+    n_visible: torch.Tensor
+    width: int
+    height: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means2d.shape[0])
+
+
+def _c32(t):
+    assert t.is_cuda and t.dtype == torch.float32, "expected a float32 CUDA tensor"
+    return t.contiguous()
+
+
+def project(means3d, scales, quats, opacities, sh, cam, cfg: RasterConfig, ws: Workspace,
+            sort: bool = True) -> Projected:
+    """gs_preprocess (projection, SH colour, culling, keys) then gs_sort."""
+    dev = means3d.device
+    n = int(means3d.shape[0])
+    cc, cm = cfg.c(), camera_c(cam)
+    means3d, scales, quats, opacities, sh = map(_c32, (means3d, scales, quats, opacities, sh))
+    out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
+               rgb=torch.empty(n, 3, device=dev), depth=torch.empty(n, device=dev),
+               keys=torch.empty(n, dtype=torch.int32, device=dev),
+               ids=torch.empty(n, dtype=torch.int32, device=dev),
+               n_visible=torch.zeros(1, dtype=torch.int32, device=dev))
+    b, nb = _ws_args(ws, max(L.gs_workspace_size("preprocess", n, cm.width, cm.height, cc), 256))
+    L.gs_preprocess(cm, cc, n, means3d, scales, quats, opacities, sh, out["means2d"],
+                    out["conics"], out["rgb"], out["depth"], out["keys"], out["ids"],
+                    out["n_visible"], b, nb, _stream(dev))
+    p = Projected(opacities=opacities, width=cm.width, height=cm.height, **out)
+    if sort:
+        sort_(p, ws)
+    return p
+
+
+def prepare_2d(means2d, conics, opacities, rgb, depth, width, height, cfg: RasterConfig,
+               ws: Workspace, sort: bool = True) -> Projected:
+    """gs_prepare_2d (keys and culling for pre-projected splats) then gs_sort."""
+    dev = means2d.device
+    n = int(means2d.shape[0])
+    cc, cm = cfg.c(), image_camera(width, height)
+    means2d, conics, opacities, rgb, depth = map(_c32, (means2d, conics, opacities, rgb, depth))
+    keys = torch.empty(n, dtype=torch.int32, device=dev)
+    ids = torch.empty(n, dtype=torch.int32, device=dev)
+    nvis = torch.zeros(1, dtype=torch.int32, device=dev)
+    b, nb = _ws_args(ws, L.gs_workspace_size("prepare_2d", n, width, height, cc))
+    L.gs_prepare_2d(cm, cc, n, means2d, conics, opacities, depth, keys, ids, nvis, b, nb,
+                    _stream(dev))
+    p = Projected(means2d=means2d, conics=conics, rgb=rgb, opacities=opacities, depth=depth,
+                  keys=keys, ids=ids, n_visible=nvis, width=width, height=height)
+    if sort:
+        sort_(p, ws)
+    return p
+
+
+def sort_(p: Projected, ws: Workspace):
+    """gs_sort: stable depth sort of the visible prefix of (keys, ids), in place."""
+    n = p.n
+    b, nb = _ws_args(ws, L.gs_workspace_size("sort", n, p.width, p.height, L.GsConfig()))
+    L.gs_sort(n, p.keys, p.ids, p.n_visible, b, nb, _stream(p.keys.device))
+
+
+def new_stats(device):
+    """Zeroed gs_stats block on the device (16 x uint64)."""
+    return torch.zeros(16, dtype=torch.int64, device=device)
+
+
+def read_stats(t) -> dict:
+    v = t.cpu().numpy().astype(np.uint64)
+    return {k: int(v[i]) for i, k in enumerate(L.STATS_FIELDS)}
+
+
+FB_BYTES = {"f32": 16, "f16": 8, "unorm16": 8, "bf16": 8, "unorm8": 4}
+
+
+def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, image=None, T=None,
+                   coverage=False, stats=None):
+    """gs_raster_fwd: returns dict(fb, image [3,H,W], T [H,W], coverage [H,W] or None)."""
+    dev = p.means2d.device
+    W, H, n = p.width, p.height, p.n
+    cc, cm = cfg.c(), image_camera(W, H)
+    if fb is None:
+        fb = torch.empty(L.gs_framebuffer_size(W, H, cfg.fb_format), dtype=torch.uint8, device=dev)
+    if image is None:
+        image = torch.empty(3, H, W, device=dev)
+    if T is None:
+        T = torch.empty(H, W, device=dev)
+    cov = torch.empty(H, W, dtype=torch.int32, device=dev) if coverage else None
+    if stats is not None:
+        cc.flags |= 1
+    b, nb = _ws_args(ws, L.gs_workspace_size("raster_fwd", n, W, H, cc))
+    L.gs_raster_fwd(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, fb,
+                    image, T, cov, stats, b, nb, _stream(dev))
+    return dict(fb=fb, image=image, T=T, coverage=cov)
+
+
+def raster_backward(p: Projected, fb, dL_dimage, cfg: RasterConfig, ws: Workspace, live=False,
+                    stats=None, out=None):
+    """gs_raster_bwd: gradients w.r.t. (means2d, conics, opacities, rgb) by splat id."""
+    dev = p.means2d.device
+    W, H, n = p.width, p.height, p.n
+    cc, cm = cfg.c(), image_camera(W, H)
+    if out is None:
+        out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
+                   opacities=torch.empty(n, device=dev), rgb=torch.empty(n, 3, device=dev))
+    lv = torch.empty(H, W, dtype=torch.int32, device=dev) if live else None
+    if stats is not None:
+        cc.flags |= 1
+    b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc))
+    L.gs_raster_bwd(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, fb,
+                    _c32(dL_dimage), out["means2d"], out["conics"], out["opacities"], out["rgb"],
+                    lv, stats, b, nb, _stream(dev))
+    out["live"] = lv
+    return out
+
+
+def project_backward(means3d, scales, quats, opacities, sh, cam, cfg: RasterConfig, g2d: dict,
+                     out=None):
+    """gs_preprocess_bwd: gradients w.r.t. the 3D Gaussian parameters."""
+    dev = means3d.device
+    n = int(means3d.shape[0])
+    cc, cm = cfg.c(), camera_c(cam)
+    if out is None:
+        out = dict(means3d=torch.empty_like(means3d), scales=torch.empty_like(scales),
+                   quats=torch.empty_like(quats), opacities=torch.empty_like(opacities),
+                   sh=torch.empty_like(sh))
+    L.gs_preprocess_bwd(cm, cc, n, _c32(means3d), _c32(scales), _c32(quats), _c32(opacities),
+                        _c32(sh), g2d["means2d"], g2d["conics"], g2d["rgb"], g2d["opacities"],
+                        out["means3d"], out["scales"], out["quats"], out["opacities"], out["sh"],
+                        _stream(dev))
+    return out
+
+
+# ---- autograd -------------------------------------------------------------------------------
+
+class GaussianRasterizeFn(torch.autograd.Function):
+    """image, T = f(means3d, scales, quats, opacities, sh): projection, depth sort, ordered
+    compositing; the backward runs Procedures 1-2 and the projection's backward. Activations
+    (exp of log-scales, sigmoid of logits) stay in torch, outside this function. The returned T
+    carries no gradient (the procedure takes only dL/dC)."""
+
+    @staticmethod
+    def forward(ctx, means3d, scales, quats, opacities, sh, cam, cfg, ws):
+        p = project(means3d, scales, quats, opacities, sh, cam, cfg, ws)
+        out = raster_forward(p, cfg, ws)
+        ctx.cam, ctx.cfg, ctx.ws, ctx.proj = cam, cfg, ws, p
+        ctx.save_for_backward(means3d, scales, quats, opacities, sh, out["fb"])
+        ctx.mark_non_differentiable(out["T"])
+        return out["image"], out["T"]
+
+    @staticmethod
+    def backward(ctx, d_image, d_T):
+        means3d, scales, quats, opacities, sh, fb = ctx.saved_tensors
+        g2 = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws)
+        g3 = project_backward(means3d, scales, quats, opacities, sh, ctx.cam, ctx.cfg, g2)
+        return g3["means3d"], g3["scales"], g3["quats"], g3["opacities"], g3["sh"], None, None, None
+
+
+class Raster2DFn(torch.autograd.Function):
+    """image, T = f(means2d, conics, opacities, rgb; depth) for splats that are already 2D."""
+
+    @staticmethod
+    def forward(ctx, means2d, conics, opacities, rgb, depth, width, height, cfg, ws):
+        p = prepare_2d(means2d, conics, opacities, rgb, depth, width, height, cfg, ws)
+        out = raster_forward(p, cfg, ws)
+        ctx.cfg, ctx.ws, ctx.proj = cfg, ws, p
+        ctx.save_for_backward(out["fb"])
+        ctx.mark_non_differentiable(out["T"])
+        return out["image"], out["T"]
+
+    @staticmethod
+    def backward(ctx, d_image, d_T):
+        (fb,) = ctx.saved_tensors
+        g = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws)
+        return g["means2d"], g["conics"], g["opacities"], g["rgb"], None, None, None, None, None
+
+
+def rasterize_gaussians(means3d, scales, quats, opacities, sh, cam, cfg=None, ws=None):
+    cfg = cfg or RasterConfig()
+    ws = ws or Workspace(means3d.device)
+    return GaussianRasterizeFn.apply(means3d, scales, quats, opacities, sh, cam, cfg, ws)
+
+
+def rasterize_2d(means2d, conics, opacities, rgb, depth, width, height, cfg=None, ws=None):
+    cfg = cfg or RasterConfig()
+    ws = ws or Workspace(means2d.device)
+    return Raster2DFn.apply(means2d, conics, opacities, rgb, depth, width, height, cfg, ws)

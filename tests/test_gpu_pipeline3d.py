@@ -1,0 +1,163 @@
+"""GPU parity of the 3D path (gs_preprocess, gs_sort, gs_raster_fwd/bwd, gs_preprocess_bwd)
+against the FP64 oracle, through the C ABI, on clustered synthetic scenes."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import group_errors, grads9, rel_l2, t
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_2505_18764_amd import render as R  # noqa: E402
+
+F32 = np.float32
+
+
+def _scene(n, seed, W, H, fx_ref=900.0, ref_w=1024):
+    sc = synth.scene3d(n, seed=seed)
+    cam = synth.camera_front(W, H, fx_ref * W / ref_w)
+    return sc, cam
+
+
+def _gpu_project(sc, cam, cfg=None):
+    cfg = cfg or R.RasterConfig()
+    ws = R.Workspace()
+    p = R.project(t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh), cam, cfg, ws)
+    torch.cuda.synchronize()
+    return p, ws
+
+
+def test_projection_parity():
+    sc, cam = _scene(40_000, 2, 320, 240)
+    p, _ = _gpu_project(sc, cam)
+    pre = oracle.preprocess(sc, cam)
+    n = sc.n
+    nv = int(p.n_visible.item())
+    ids = p.ids.cpu().numpy()
+    keys = p.keys.cpu().numpy().view(np.uint32)
+    gvis = np.zeros(n, bool)
+    gvis[ids[:nv]] = True
+    ovis = pre["visible"]
+    diff = np.flatnonzero(gvis != ovis)
+    assert np.all(pre["ambiguous"][diff]), diff[:10]          # only borderline frustum decisions
+    assert ovis.sum() > 0.5 * n
+    assert sorted(ids) == list(range(n))
+    # sort order: bit-exact on the splats both sides keep
+    both = gvis & ovis
+    g_order = ids[:nv][both[ids[:nv]]]
+    o_order = oracle.visible_order(pre["keys"])
+    o_order = o_order[both[o_order]]
+    np.testing.assert_array_equal(g_order, o_order)
+    np.testing.assert_array_equal(keys[:nv][both[ids[:nv]]], pre["keys"][g_order])
+    # per-splat outputs
+    depth = p.depth.cpu().numpy()
+    np.testing.assert_array_equal(depth[both], pre["tz"][both].astype(F32))
+    m2 = p.means2d.cpu().numpy()[both]
+    np.testing.assert_allclose(m2, pre["means2d"][both], rtol=2e-6, atol=1e-3)
+    cn = p.conics.cpu().numpy()[both]
+    ref = pre["conic"][both]
+    scale = np.abs(ref).max(axis=1, keepdims=True)
+    assert (np.abs(cn - ref) / scale).max() < 1e-3
+    assert rel_l2(cn, ref) < 1e-5
+    np.testing.assert_allclose(p.rgb.cpu().numpy()[both], pre["rgb"][both], atol=2e-6)
+    cul = ~gvis
+    assert (p.means2d.cpu().numpy()[cul] == 0).all() and (depth[cul] == 0).all()
+
+
+def test_projection_backward_parity():
+    sc, cam = _scene(4000, 5, 256, 192)
+    sc.means3d *= 0.7
+    n = sc.n
+    g = np.random.default_rng(3)
+    gm, gc = g.normal(size=(n, 2)).astype(F32), (g.normal(size=(n, 3)) * 1e3).astype(F32)
+    gr, go = g.normal(size=(n, 3)).astype(F32), g.normal(size=n).astype(F32)
+    cfg = R.RasterConfig()
+    g2d = dict(means2d=t(gm), conics=t(gc), rgb=t(gr), opacities=t(go))
+    out = R.project_backward(t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh),
+                             cam, cfg, g2d)
+    torch.cuda.synchronize()
+    ref = oracle.preprocess_vjp(sc, cam, gm, gc, gr, go)
+    pre = oracle.preprocess(sc, cam)
+    keep = pre["visible"] & ~pre["ambiguous"]
+    for k in ("means3d", "scales", "quats", "opacities", "sh"):
+        a = out[k].cpu().numpy()[keep]
+        b = ref[k][keep]
+        e = rel_l2(a, b)
+        print(k, e)
+        assert e < 2e-4, (k, e)
+    assert (out["means3d"].cpu().numpy()[~pre["visible"] & ~pre["ambiguous"]] == 0).all()
+
+
+def _oracle_projected(sc, cam):
+    """Raster inputs from the oracle's projection (rounded to FP32) and its depth order."""
+    pre = oracle.preprocess(sc, cam)
+    order = oracle.visible_order(pre["keys"])
+    cul = np.setdiff1d(np.arange(sc.n), order)
+    ids = np.concatenate([order, cul]).astype(np.int32)
+    arr = dict(means2d=pre["means2d"].astype(F32), conics=pre["conic"].astype(F32),
+               rgb=pre["rgb"].astype(F32), opacities=sc.opacities.astype(F32))
+    return pre, order, ids, arr
+
+
+@pytest.mark.parametrize("fmt,mode", [("f32", "hybrid"), ("f32", "hybrid_lane"), ("f32", "naive")])
+def test_raster_on_projected_scene(fmt, mode):
+    """The raster stage alone on a dense clustered scene (depth complexity in the hundreds)."""
+    sc, cam = _scene(60_000, 7, 256, 192)
+    W, H = cam.width, cam.height
+    pre, order, ids, arr = _oracle_projected(sc, cam)
+    G = synth.image_grad(W, H, 17)
+    p = R.Projected(means2d=t(arr["means2d"]), conics=t(arr["conics"]), rgb=t(arr["rgb"]),
+                    opacities=t(arr["opacities"]), depth=t(np.zeros(sc.n, F32)),
+                    keys=t(np.zeros(sc.n, np.int32)), ids=t(ids),
+                    n_visible=t(np.array([len(order)], np.int32)), width=W, height=H)
+    cfg = R.RasterConfig(fb_format=fmt, reduce_mode=mode)
+    ws = R.Workspace()
+    st = R.new_stats("cuda")
+    f = R.raster_forward(p, cfg, ws, coverage=True, stats=st)
+    b = R.raster_backward(p, f["fb"], t(G), cfg, ws, live=True, stats=st)
+    torch.cuda.synchronize()
+    ref = oracle.raster(arr["means2d"], arr["conics"], arr["opacities"], arr["rgb"], order, W, H,
+                        dL_dimg=G, cfg=oracle.OracleConfig(beta=1e-6, beta_abs=4e-6, tau=1e-4))
+    ok = ref["amb"] == 0
+    assert ok.mean() > 0.9
+    img = f["image"].cpu().numpy()
+    assert np.abs(img - ref["img"])[:, ok].max() <= 1e-5
+    np.testing.assert_array_equal(f["coverage"].cpu().numpy()[ok], ref["cov"][ok])
+    np.testing.assert_array_equal(b["live"].cpu().numpy()[ok], ref["live"][ok])
+    e = group_errors(grads9(b), ref["grad"])
+    st = R.read_stats(st)
+    print(mode, e, st, "mean covered/px", ref["cov"].mean(), "mean live/px", ref["live"].mean())
+    assert e["all"] <= 1e-4, e
+    assert ref["cov"].mean() > 20
+
+
+def test_end_to_end_chain():
+    """GPU projection -> sort -> raster fwd/bwd -> projection bwd against the oracle's own chain
+    (FP64 projection, FP64 raster, complex-step projection backward)."""
+    sc, cam = _scene(20_000, 9, 192, 144)
+    W, H = cam.width, cam.height
+    G = synth.image_grad(W, H, 19)
+    cfg = R.RasterConfig()
+    ws = R.Workspace()
+    args = [t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh)]
+    p = R.project(*args, cam, cfg, ws)
+    f = R.raster_forward(p, cfg, ws)
+    b = R.raster_backward(p, f["fb"], t(G), cfg, ws)
+    g3 = R.project_backward(*args, cam, cfg, b)
+    torch.cuda.synchronize()
+    ocfg = oracle.OracleConfig(beta=1e-5, beta_abs=2e-3, tau=1e-3)
+    ref = oracle.render_scene(sc, cam, dL_dimg=G, cfg=ocfg)
+    ok = ref["amb"] == 0
+    img = f["image"].cpu().numpy()
+    d = np.abs(img - ref["img"])[:, ok].max()
+    print("end-to-end image max-abs (unflagged)", d, "flagged px", (~ok).mean())
+    assert d <= 1e-4
+    og = ref["grad"]
+    ov = oracle.preprocess_vjp(sc, cam, og[:, 0:2], og[:, 2:5], og[:, 6:9], og[:, 5])
+    errs = {k: rel_l2(g3[k].cpu().numpy(), ov[k]) for k in ov}
+    allg = rel_l2(np.concatenate([g3[k].cpu().numpy().reshape(-1) for k in ov]),
+                  np.concatenate([ov[k].reshape(-1) for k in ov]))
+    print("end-to-end 3D gradient rel-L2", errs, "all", allg)
+    assert allg <= 1e-3
