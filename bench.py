@@ -194,7 +194,8 @@ def main():
                       "live_per_s": round(Lv / (bwd_ms * 1e-3), 1),
                       "atomic_rate": round(st["bwd_atomic_sets"] / max(1, Lv), 5),
                       "cohesion": round(st["bwd_cohesive"] / max(1, st["bwd_wave_reductions"] +
-                                                                   st["bwd_quad_reductions"]), 4)},
+                                                                   st["bwd_quad_reductions"]), 4),
+                      "stats": st},
         "roofline": dict(roof[dom], kernel=dom),
         "roofline_kernels": roof,
         "workspace_bytes": head["ws_bytes"],

@@ -143,20 +143,19 @@ size_t gs_framebuffer_size(int32_t width, int32_t height, int32_t fb_format) {
 
 size_t gs_workspace_size(int32_t op, int32_t n, int32_t width, int32_t height, const gs_config* cfg) {
     if (n < 0 || n > MAX_N) return 0;
-    (void)width;
-    (void)height;
+    if (width < 1 || width > MAX_DIM || height < 1 || height > MAX_DIM) return 0;
     (void)cfg;
     switch (op) {
     case GS_OP_PREPROCESS:
     case GS_OP_PREPARE_2D: return preprocess_ws(n);
     case GS_OP_SORT: return gsr::sort_ws_bytes(n, 4);
-    case GS_OP_RASTER_FWD: return gsr::raster_ws_bytes(n, false);
-    case GS_OP_RASTER_BWD: return gsr::raster_ws_bytes(n, true);
+    case GS_OP_RASTER_FWD: return gsr::raster_ws_bytes(n, width, height, false);
+    case GS_OP_RASTER_BWD: return gsr::raster_ws_bytes(n, width, height, true);
     case GS_OP_PREPROCESS_BWD: return 0;
     case GS_OP_ALL: {
         size_t m = preprocess_ws(n);
         size_t s = gsr::sort_ws_bytes(n, 4);
-        size_t r = gsr::raster_ws_bytes(n, true);
+        size_t r = gsr::raster_ws_bytes(n, width, height, true);
         if (s > m) m = s;
         if (r > m) m = r;
         return m;
@@ -230,7 +229,7 @@ int gs_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const i
     if (n > 0) {
         GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
     }
-    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, false)));
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, false)));
     return hip_status(gsr::launch_raster_fwd(*cfg, cam->width, cam->height, n, sorted_ids,
                                              n_visible, means2d, conics, opacities, rgb, fb,
                                              out_rgb, out_T, out_coverage, stats, ws,
@@ -254,7 +253,7 @@ int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const i
         GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
         GSR_NEED(dL_dmeans2d); GSR_NEED(dL_dconics); GSR_NEED(dL_dopacities); GSR_NEED(dL_drgb);
     }
-    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, true)));
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, true)));
     return hip_status(gsr::launch_raster_bwd(*cfg, cam->width, cam->height, n, sorted_ids,
                                              n_visible, means2d, conics, opacities, rgb, fb,
                                              dL_dimage, dL_dmeans2d, dL_dconics, dL_dopacities,

@@ -33,9 +33,11 @@ struct RasterWs {
     void* rect;        // [n] uint2 tile rectangles
     float* grad;       // [n * GRAD_STRIDE] (backward only)
     unsigned long long* counters;  // [16] stats scratch
+    uint32_t* weights; // [tiles] sampled splat count per tile
+    int32_t* order;    // [tiles] tiles by decreasing weight
 };
-size_t raster_ws_bytes(int n, bool bwd);
-RasterWs carve_raster_ws(void* ws, int n, bool bwd);
+size_t raster_ws_bytes(int n, int width, int height, bool bwd);
+RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd);
 
 size_t sort_ws_bytes(int n, int key_bytes);
 size_t compact_ws_bytes(int n);

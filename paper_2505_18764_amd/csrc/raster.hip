@@ -25,9 +25,11 @@ constexpr int SPAN = 1024;         // sorted splats one wave tests per fill
 constexpr int CHUNK = 4 * SPAN;    // sorted splats the workgroup tests per fill
 constexpr int BATCH = 256;         // splat records staged in LDS at once
 
-// A staged splat: a = (mean x, mean y, conic a, conic b); b = (conic c, opacity, r, g);
+// A staged splat: a = (mean x, mean y, a', b'); b = (c', opacity, r, g);
 // c = (bits of colour b, sorted position, x0 | x1 << 16, y0 | y1 << 16) with the pixel bounding
-// box [x0, x1) x [y0, y1) of the alpha >= alpha_min ellipse, clamped to the image.
+// box [x0, x1) x [y0, y1) of the alpha >= alpha_min ellipse, clamped to the image. The conic is
+// stored pre-scaled, (a', b', c') = -log2(e) (a/2, b, c/2), so that the exponent of
+// alpha = o 2^p is p = dx (a' dx + b' dy) + c' dy^2 = -q/2 log2(e).
 struct __align__(16) Rec {
     float4 a;
     float4 b;
@@ -35,11 +37,43 @@ struct __align__(16) Rec {
 };
 static_assert(sizeof(Rec) == REC_BYTES, "record size");
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run of
-// tiles so that the splat records two neighbouring tiles share meet in one L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks, int ntiles) {
-    const int per = nblocks / 8;   // nblocks is a multiple of 8
-    return (bid % 8) * per + bid / 8;
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr int WEIGHT_SAMPLE = 8;        // every 8th sorted splat votes for the tiles it touches
+constexpr int MAX_ORDERED_TILES = 4096; // tiles ordered by weight in one workgroup (LDS sort)
+
+// Tile schedule. The work of a tile grows with the number of splats over it, which on clustered
+// scenes varies by orders of magnitude across the screen. Workgroups are dispatched in block
+// order (round-robin over the 8 XCDs, then to whichever CU has room), so listing the tiles by
+// decreasing estimated work starts the heaviest tiles first and spreads them over all XCDs:
+// a longest-processing-time-first schedule.
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ weights,
+                                                     int ntiles, int32_t* __restrict__ order) {
+    __shared__ unsigned long long key[MAX_ORDERED_TILES];
+    const int tid = threadIdx.x;
+    if (ntiles > MAX_ORDERED_TILES) {
+        for (int i = tid; i < ntiles; i += blockDim.x) order[i] = i;
+        return;
+    }
+    int m = 1;
+    while (m < ntiles) m <<= 1;
+    for (int i = tid; i < m; i += blockDim.x)
+        key[i] = i < ntiles ? ((unsigned long long)(0xFFFFFFFFu - weights[i]) << 32) | (uint32_t)i
+                            : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1) {          // bitonic sort, ascending
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < m; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) { key[i] = b; key[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < ntiles; i += blockDim.x) order[i] = (int32_t)(key[i] & 0xFFFFFFFFu);
 }
 
 __device__ __forceinline__ bool rect_hit(uint2 r, uint32_t tx, uint32_t ty) {
@@ -56,7 +90,8 @@ __global__ __launch_bounds__(256) void k_raster_setup(
     int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
     const float* __restrict__ means2d, const float* __restrict__ conics,
     const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
-    int saturate, Rec* __restrict__ rec, uint2* __restrict__ rect) {
+    int saturate, int tiles_x, Rec* __restrict__ rec, uint2* __restrict__ rect,
+    uint32_t* __restrict__ weights) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     int nvis = *nvis_ptr;
@@ -88,12 +123,17 @@ __global__ __launch_bounds__(256) void k_raster_setup(
                     const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
                     const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
                     Rec r;
-                    r.a = make_float4(mx, my, a, b);
-                    r.b = make_float4(c, o, cr, cg);
+                    r.a = make_float4(mx, my, -0.5f * LOG2E * a, -LOG2E * b);
+                    r.b = make_float4(-0.5f * LOG2E * c, o, cr, cg);
                     r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, x0 | (x1 << 16), y0 | (y1 << 16));
                     rec[p] = r;
-                    rr = make_uint2((x0 / TILE) | (((x1 - 1) / TILE) << 16),
-                                    (y0 / TILE) | (((y1 - 1) / TILE) << 16));
+                    const uint32_t tx0 = x0 / TILE, tx1 = (x1 - 1) / TILE;
+                    const uint32_t ty0 = y0 / TILE, ty1 = (y1 - 1) / TILE;
+                    rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                    if (p % WEIGHT_SAMPLE == 0 && (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 64)
+                        for (uint32_t ty = ty0; ty <= ty1; ++ty)
+                            for (uint32_t tx = tx0; tx <= tx1; ++tx)
+                                atomicAdd(&weights[ty * (uint32_t)tiles_x + tx], 1u);
                 }
             }
         }
@@ -158,13 +198,12 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
 template <int RFMT, bool TCULL, bool INSTR>
 __global__ __launch_bounds__(NT) void k_raster_fwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
-    const uint2* __restrict__ rect, int W, int H, int tiles_x, int ntiles, float amin, float amax,
-    float tmin, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
+    const uint2* __restrict__ rect, const int32_t* __restrict__ order, int W, int H, int tiles_x,
+    float amin, float amax, float tmin, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
     float* __restrict__ out_T, int32_t* __restrict__ out_cov,
     unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles);
-    if (tile >= ntiles) return;
+    const int tile = order[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
@@ -216,8 +255,8 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
                         if (x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy &&
                             (!TCULL || ((alive >> s) & 1u))) {
                             const float dx = px[s] - A.x, dy = py[s] - A.y;
-                            const float q = dx * fmaf(A.z, dx, 2.f * A.w * dy) + B.x * dy * dy;
-                            const float al = fminf(amax, B.y * __expf(-0.5f * q));
+                            const float pw = fmaf(dx, fmaf(A.z, dx, A.w * dy), B.x * dy * dy);
+                            const float al = fminf(amax, B.y * __builtin_amdgcn_exp2f(pw));
                             bool pass = al >= amin;
                             if (TCULL) pass = pass && T[s] >= tmin;
                             if (pass) {
@@ -334,13 +373,13 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
 template <int RFMT, bool INSTR>
 __global__ __launch_bounds__(NT) void k_raster_bwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
-    const uint2* __restrict__ rect, int W, int H, int tiles_x, int ntiles, float amin, float amax,
-    float tmin, int fb_fmt, const void* __restrict__ fb, const float* __restrict__ dL_dimg,
+    const uint2* __restrict__ rect, const int32_t* __restrict__ order, int W, int H, int tiles_x,
+    float amin, float amax, float tmin, int fb_fmt, const void* __restrict__ fb,
+    const float* __restrict__ dL_dimg,
     int mode, int X, float* __restrict__ grad, int32_t* __restrict__ out_live,
     unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x, ntiles);
-    if (tile >= ntiles) return;
+    const int tile = order[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
@@ -408,8 +447,8 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                     if (!(x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy && ((alive >> s) & 1u)))
                         continue;
                     const float dx = px[s] - A.x, dy = py[s] - A.y;
-                    const float q = dx * fmaf(A.z, dx, 2.f * A.w * dy) + B.x * dy * dy;
-                    const float e = __expf(-0.5f * q);
+                    const float pw = fmaf(dx, fmaf(A.z, dx, A.w * dy), B.x * dy * dy);
+                    const float e = __builtin_amdgcn_exp2f(pw);       // exp(-q/2)
                     const float araw = B.y * e;
                     const float al = fminf(amax, araw);
                     // cullingFlag: splat boundary (alpha < 1/255), then T-Culling (T < 1e-4)
@@ -439,12 +478,14 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                             Cp[s][2] = fb_round<RFMT>(Cp[s][2]);
                             T[s] = fb_round<RFMT>(T[s]);
                         }
-                        // bwd_diff: alpha = o exp(-q/2) (zero gradient where clamped)
+                        // bwd_diff: alpha = o exp(-q/2) (zero gradient where clamped);
+                        // dq/dmu = -2 Q d, written with the pre-scaled conic
                         if (araw < amax) {
-                            const float gq = -0.5f * ga * araw;
+                            const float gq = -0.5f * ga * araw;          // dL/dq
+                            const float gm = -ga * araw * (1.0f / LOG2E);
                             g[5] = ga * e;
-                            g[0] = -2.f * gq * fmaf(A.z, dx, A.w * dy);
-                            g[1] = -2.f * gq * fmaf(A.w, dx, B.x * dy);
+                            g[0] = gm * fmaf(2.f * A.z, dx, A.w * dy);
+                            g[1] = gm * fmaf(A.w, dx, 2.f * B.x * dy);
                             g[2] = gq * dx * dx;
                             g[3] = 2.f * gq * dx * dy;
                             g[4] = gq * dy * dy;
@@ -533,28 +574,57 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
 
 // ---- host side -------------------------------------------------------------------------------
 
-size_t raster_ws_bytes(int n, bool bwd) {
-    size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up(16 * 8);
+static int tiles_of(int width, int height) {
+    return ((width + TILE - 1) / TILE) * ((height + TILE - 1) / TILE);
+}
+
+size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
+    const size_t nt = (size_t)tiles_of(width, height);
+    size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up(16 * 8) +
+               align_up(nt * 4) * 2;
     if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4);
     return b;
 }
 
-RasterWs carve_raster_ws(void* ws, int n, bool bwd) {
+RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
+    const size_t nt = (size_t)tiles_of(width, height);
     RasterWs r;
     char* p = (char*)ws;
     r.rec = p;      p += align_up((size_t)n * REC_BYTES);
     r.rect = p;     p += align_up((size_t)n * 8);
     r.counters = (unsigned long long*)p; p += align_up(16 * 8);
+    r.weights = (uint32_t*)p; p += align_up(nt * 4);
+    r.order = (int32_t*)p;    p += align_up(nt * 4);
     r.grad = bwd ? (float*)p : nullptr;
     return r;
+}
+
+// Records, tile rectangles, tile weights and the tile schedule.
+static hipError_t raster_setup(const gs_config& cfg, int width, int height, int n,
+                               const int32_t* sorted_ids, const int32_t* n_visible,
+                               const float* means2d, const float* conics, const float* opac,
+                               const float* rgb, const RasterWs& r, hipStream_t s) {
+    const int tiles_x = (width + TILE - 1) / TILE;
+    const int ntiles = tiles_of(width, height);
+    hipError_t e = launch_fill_u32(r.weights, (size_t)ntiles, 0u, s);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        const int sat = (cfg.fb_format == FB_UNORM16 || cfg.fb_format == FB_UNORM8) ? 1 : 0;
+        hipLaunchKernelGGL(k_raster_setup, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
+                           n_visible, means2d, conics, opac, rgb, width, height, cfg.alpha_min,
+                           sat, tiles_x, (Rec*)r.rec, (uint2*)r.rect, r.weights);
+    }
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, r.weights, ntiles, r.order);
+    return hipGetLastError();
 }
 
 static bool saturating(int fmt) { return fmt == FB_UNORM16 || fmt == FB_UNORM8; }
 
 template <bool TC, bool IN>
-static void fwd_by_fmt(int rfmt, void (*&k)(int, const int32_t*, const Rec*, const uint2*, int, int,
-                                             int, int, float, float, float, int, void*, float*,
-                                             float*, int32_t*, unsigned long long*)) {
+static void fwd_by_fmt(int rfmt, void (*&k)(int, const int32_t*, const Rec*, const uint2*,
+                                             const int32_t*, int, int, int, float, float, float, int,
+                                             void*, float*, float*, int32_t*,
+                                             unsigned long long*)) {
     switch (rfmt) {
     case FB_F32: k = k_raster_fwd<FB_F32, TC, IN>; break;
     case FB_F16: k = k_raster_fwd<FB_F16, TC, IN>; break;
@@ -570,25 +640,23 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                              const float* means2d, const float* conics, const float* opac,
                              const float* rgb, void* fb, float* out_rgb, float* out_T,
                              int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s) {
-    const RasterWs r = carve_raster_ws(ws, n, false);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_raster_setup, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
-                           n_visible, means2d, conics, opac, rgb, width, height, cfg.alpha_min,
-                           (int)saturating(cfg.fb_format), (Rec*)r.rec, (uint2*)r.rect);
-    }
-    const int tiles_x = (width + TILE - 1) / TILE, tiles_y = (height + TILE - 1) / TILE;
-    const int ntiles = tiles_x * tiles_y;
-    const int nblocks = (ntiles + 7) / 8 * 8;
+    const RasterWs r = carve_raster_ws(ws, n, width, height, false);
+    hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
+                                 opac, rgb, r, s);
+    if (e0 != hipSuccess) return e0;
+    const int tiles_x = (width + TILE - 1) / TILE;
+    const int nblocks = tiles_of(width, height);
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool tcull = cfg.t_min_fwd > 0.f;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_cov;
-    void (*k)(int, const int32_t*, const Rec*, const uint2*, int, int, int, int, float, float, float,
-              int, void*, float*, float*, int32_t*, unsigned long long*) = nullptr;
+    void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, int, int, int, float,
+              float, float, int, void*, float*, float*, int32_t*, unsigned long long*) = nullptr;
     if (tcull) { if (instr) fwd_by_fmt<true, true>(rfmt, k); else fwd_by_fmt<true, false>(rfmt, k); }
     else { if (instr) fwd_by_fmt<false, true>(rfmt, k); else fwd_by_fmt<false, false>(rfmt, k); }
     hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
-                       (const uint2*)r.rect, width, height, tiles_x, ntiles, cfg.alpha_min,
-                       cfg.alpha_max, cfg.t_min_fwd, cfg.fb_format, fb, out_rgb, out_T, out_cov,
+                       (const uint2*)r.rect, (const int32_t*)r.order, width, height, tiles_x,
+                       cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.fb_format, fb, out_rgb, out_T,
+                       out_cov,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
     return hipGetLastError();
 }
@@ -599,23 +667,22 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                              const float* rgb, const void* fb, const float* dL_dimg,
                              float* g_means2d, float* g_conics, float* g_opac, float* g_rgb,
                              int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s) {
-    const RasterWs r = carve_raster_ws(ws, n, true);
+    const RasterWs r = carve_raster_ws(ws, n, width, height, true);
     const int sat = (int)saturating(cfg.fb_format);
     if (n > 0) {
         hipError_t e = launch_fill_u32(r.grad, (size_t)n * GRAD_STRIDE, 0u, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_raster_setup, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
-                           n_visible, means2d, conics, opac, rgb, width, height, cfg.alpha_min,
-                           sat, (Rec*)r.rec, (uint2*)r.rect);
     }
-    const int tiles_x = (width + TILE - 1) / TILE, tiles_y = (height + TILE - 1) / TILE;
-    const int ntiles = tiles_x * tiles_y;
-    const int nblocks = (ntiles + 7) / 8 * 8;
+    hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
+                                 opac, rgb, r, s);
+    if (e0 != hipSuccess) return e0;
+    const int tiles_x = (width + TILE - 1) / TILE;
+    const int nblocks = tiles_of(width, height);
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_live;
-    void (*k)(int, const int32_t*, const Rec*, const uint2*, int, int, int, int, float, float, float,
-              int, const void*, const float*, int, int, float*, int32_t*, unsigned long long*) =
-        nullptr;
+    void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, int, int, int, float,
+              float, float, int, const void*, const float*, int, int, float*, int32_t*,
+              unsigned long long*) = nullptr;
 #define GSR_BWD_PICK(IN)                                             \
     switch (rfmt) {                                                  \
     case FB_F32: k = k_raster_bwd<FB_F32, IN>; break;                \
@@ -628,8 +695,9 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     if (instr) { GSR_BWD_PICK(true) } else { GSR_BWD_PICK(false) }
 #undef GSR_BWD_PICK
     hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
-                       (const uint2*)r.rect, width, height, tiles_x, ntiles, cfg.alpha_min,
-                       cfg.alpha_max, cfg.t_min_bwd, cfg.fb_format, fb, dL_dimg, cfg.reduce_mode,
+                       (const uint2*)r.rect, (const int32_t*)r.order, width, height, tiles_x,
+                       cfg.alpha_min, cfg.alpha_max, cfg.t_min_bwd, cfg.fb_format, fb, dL_dimg,
+                       cfg.reduce_mode,
                        cfg.reduce_threshold, r.grad, out_live,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
     hipError_t e = hipGetLastError();
