@@ -36,10 +36,11 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
     ap.add_argument("--formats", default="f16,f32")
-    ap.add_argument("--reduce", default="hybrid")
+    ap.add_argument("--reduce", default="hybrid_lane")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-blocks", type=int, default=12)
     ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")
+    ap.add_argument("--no-tile", action="store_true", help="skip the tile-based baseline")
     return ap.parse_args()
 
 
@@ -134,9 +135,44 @@ def main():
         return dict(fmt=fmt, ms_per_view=total, wall_ms_per_view=wall, stages_ms=per,
                     stats=stats, n_visible=nvis, ws_bytes=ws.nbytes)
 
+    def run_tile(steps=max(3, args.steps // 2), warmup=1):
+        """The tile-based comparison rasterizer on the same view: projection, per-splat tile
+        counts, host readback of the pair count, pair duplication + 64-bit sort + ranges +
+        forward, backward, projection backward. Buffers are sized in the warmup, so the timed
+        steps allocate nothing (the paper's tile-based timings also exclude allocation)."""
+        cfg = R.RasterConfig(fb_format="f32")
+        ws = R.Workspace(dev)
+        q = R.project(*inp, cam, cfg, ws, sort=False)
+        f = R.tile_forward(q, cfg, ws)
+        g2 = R.tile_backward(q, f, Gd, cfg, ws)
+        g3 = R.project_backward(*inp, cam, cfg, g2)
+        torch.cuda.synchronize()
+        times = []
+        for i in range(warmup + steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+            ev[0].record()
+            q = R.project(*inp, cam, cfg, ws, sort=False)
+            ev[1].record()
+            ff = R.tile_forward(q, cfg, ws, out=f)      # includes the pair-count readback
+            ev[2].record()
+            R.tile_backward(q, ff, Gd, cfg, ws, out=g2)
+            ev[3].record()
+            R.project_backward(*inp, cam, cfg, g2, out=g3)
+            ev[4].record()
+            torch.cuda.synchronize()
+            if i >= warmup:
+                times.append([ev[j].elapsed_time(ev[j + 1]) for j in range(4)])
+        med = np.median(np.array(times), axis=0)
+        names = ["preprocess", "tile_fwd_incl_readback", "tile_bwd", "preprocess_bwd"]
+        return {"ms_per_view": float(med.sum()),
+                "stages_ms": {k: round(float(v), 4) for k, v in zip(names, med)},
+                "n_pairs": int(ff["n_pairs"]),
+                "pair_buffer_bytes": int(ff["capacity"]) * 12 * 2, "ws_bytes": ws.nbytes}
+
     results = {}
     for fmt in args.formats.split(","):
         results[fmt] = run_format(fmt, args.reduce)
+    tile = run_tile() if not args.no_tile else None
     head_fmt = "f16" if "f16" in results else list(results)[0]
     head = results[head_fmt]
     st = head["stats"]
@@ -199,6 +235,7 @@ def main():
         "roofline": dict(roof[dom], kernel=dom),
         "roofline_kernels": roof,
         "workspace_bytes": head["ws_bytes"],
+        "tile_baseline": tile,
         "cpu_baseline": cpu,
     }
     line.update(extra)

@@ -257,6 +257,50 @@ int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
                       float* dL_dmeans3d, float* dL_dscales, float* dL_dquats,
                       float* dL_dopacities, float* dL_dsh, void* stream);
 
+/* ---- Comparison design: tile-based software rasterization (Sec. 2.1.3-2.1.4) ----------------
+ *
+ * 16x16-pixel tiles. Each visible splat is duplicated into one (tile, depth key) pair per tile its
+ * alpha >= alpha_min bounding box touches; the pairs are radix-sorted by the 64-bit key (stable,
+ * so equal depths stay in input order) and cut into per-tile ranges; the forward composites each
+ * pixel front to back with T-culling at cfg->t_min_bwd (a fragment is skipped when T before it
+ * is below the threshold) and records the number of range entries up to its last blended
+ * fragment; the backward walks each pixel's range back to front from that entry, recovering T by
+ * division by (1 - alpha), and adds each fragment's 9 gradients with its own atomics (Eq. 3 and
+ * Eq. 4). It computes the same function as gs_raster_fwd/bwd with t_min_fwd = t_min_bwd, in FP32
+ * state (fb_format only selects colour saturation for the unorm formats).
+ *
+ * Protocol (the pair count is data dependent, the dynamic allocation of Sec. 1):
+ *   1. gs_tile_prepare(...) with a workspace of gs_tile_workspace_size(n, 0, W, H) bytes or more
+ *      writes the pair count to n_pairs [1] (device uint32);
+ *   2. the caller reads n_pairs back and provides a workspace of
+ *      gs_tile_workspace_size(n, capacity, W, H) bytes with capacity >= n_pairs (the first
+ *      bytes must be the same workspace as in step 1: they carry the per-splat tile counts);
+ *   3. gs_tile_raster_fwd(...) then gs_tile_raster_bwd(...) with the same workspace and capacity
+ *      (the sorted pairs and tile ranges pass from the forward to the backward).
+ * If capacity < *n_pairs the excess pairs are dropped (no out-of-bounds write; results are then
+ * incomplete). ids/keys/n_visible are gs_preprocess's or gs_prepare_2d's (sorted or not).
+ * Outputs: out_rgb [3,H,W], out_T [H,W], n_contrib [H,W] int32; gradients as gs_raster_bwd.
+ */
+size_t gs_tile_workspace_size(int32_t n, int64_t pair_capacity, int32_t width, int32_t height);
+
+int gs_tile_prepare(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* ids,
+                    const int32_t* n_visible, const float* means2d, const float* conics,
+                    const float* opacities, uint32_t* n_pairs, void* ws, size_t ws_bytes,
+                    void* stream);
+
+int gs_tile_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* ids,
+                       const uint32_t* keys, const float* means2d, const float* conics,
+                       const float* opacities, const float* rgb, const uint32_t* n_pairs,
+                       int64_t pair_capacity, float* out_rgb, float* out_T, int32_t* n_contrib,
+                       void* ws, size_t ws_bytes, void* stream);
+
+int gs_tile_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
+                       const float* means2d, const float* conics, const float* opacities,
+                       const float* rgb, const float* dL_dimage, const float* T_final,
+                       const int32_t* n_contrib, int64_t pair_capacity, float* dL_dmeans2d,
+                       float* dL_dconics, float* dL_dopacities, float* dL_drgb, void* ws,
+                       size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

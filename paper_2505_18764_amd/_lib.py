@@ -77,6 +77,15 @@ _SIGS = {
     "gs_preprocess_bwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                          c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
                                          c_p, c_p, c_p, c_p]),
+    "gs_tile_workspace_size": (c_sz, [c_i, ctypes.c_int64, c_i, c_i]),
+    "gs_tile_prepare": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
+                                       c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_tile_raster_fwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
+                                          c_p, c_p, c_p, c_p, c_p, c_p, c_p, ctypes.c_int64, c_p,
+                                          c_p, c_p, c_p, c_sz, c_p]),
+    "gs_tile_raster_bwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
+                                          c_p, c_p, c_p, c_p, c_p, c_p, c_p, ctypes.c_int64, c_p,
+                                          c_p, c_p, c_p, c_p, c_sz, c_p]),
 }
 
 
@@ -184,3 +193,32 @@ def gs_preprocess_bwd(cam: GsCamera, cfg: GsConfig, n, means3d, scales, quats, o
         _ptr(opacities), _ptr(sh), _ptr(dL_dmeans2d), _ptr(dL_dconics), _ptr(dL_drgb),
         _ptr(dL_dopacities2d), _ptr(dL_dmeans3d), _ptr(dL_dscales), _ptr(dL_dquats),
         _ptr(dL_dopacities), _ptr(dL_dsh), stream))
+
+
+def gs_tile_workspace_size(n, pair_capacity, width, height) -> int:
+    return int(lib().gs_tile_workspace_size(n, pair_capacity, width, height))
+
+
+def gs_tile_prepare(cam: GsCamera, cfg: GsConfig, n, ids, n_visible, means2d, conics, opacities,
+                    n_pairs, ws, ws_bytes, stream):
+    _check("gs_tile_prepare", lib().gs_tile_prepare(
+        ctypes.byref(cam), ctypes.byref(cfg), n, _ptr(ids), _ptr(n_visible), _ptr(means2d),
+        _ptr(conics), _ptr(opacities), _ptr(n_pairs), _ptr(ws), ws_bytes, stream))
+
+
+def gs_tile_raster_fwd(cam: GsCamera, cfg: GsConfig, n, ids, keys, means2d, conics, opacities, rgb,
+                       n_pairs, pair_capacity, out_rgb, out_T, n_contrib, ws, ws_bytes, stream):
+    _check("gs_tile_raster_fwd", lib().gs_tile_raster_fwd(
+        ctypes.byref(cam), ctypes.byref(cfg), n, _ptr(ids), _ptr(keys), _ptr(means2d),
+        _ptr(conics), _ptr(opacities), _ptr(rgb), _ptr(n_pairs), pair_capacity, _ptr(out_rgb),
+        _ptr(out_T), _ptr(n_contrib), _ptr(ws), ws_bytes, stream))
+
+
+def gs_tile_raster_bwd(cam: GsCamera, cfg: GsConfig, n, means2d, conics, opacities, rgb,
+                       dL_dimage, T_final, n_contrib, pair_capacity, dL_dmeans2d, dL_dconics,
+                       dL_dopacities, dL_drgb, ws, ws_bytes, stream):
+    _check("gs_tile_raster_bwd", lib().gs_tile_raster_bwd(
+        ctypes.byref(cam), ctypes.byref(cfg), n, _ptr(means2d), _ptr(conics), _ptr(opacities),
+        _ptr(rgb), _ptr(dL_dimage), _ptr(T_final), _ptr(n_contrib), pair_capacity,
+        _ptr(dL_dmeans2d), _ptr(dL_dconics), _ptr(dL_dopacities), _ptr(dL_drgb), _ptr(ws),
+        ws_bytes, stream))

@@ -21,7 +21,7 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster.hip", "tile.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

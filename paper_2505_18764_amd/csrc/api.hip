@@ -283,4 +283,79 @@ int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, con
                       "gs_preprocess_bwd");
 }
 
+// ---- tile-based comparison rasterizer --------------------------------------------------------
+
+size_t gs_tile_workspace_size(int32_t n, int64_t pair_capacity, int32_t width, int32_t height) {
+    if (n < 0 || n > MAX_N || pair_capacity < 0 || pair_capacity > (int64_t)1 << 31) return 0;
+    if (width < 1 || width > MAX_DIM || height < 1 || height > MAX_DIM) return 0;
+    return gsr::tile_ws_bytes(n, (size_t)pair_capacity, width, height);
+}
+
+int gs_tile_prepare(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* ids,
+                    const int32_t* n_visible, const float* means2d, const float* conics,
+                    const float* opacities, uint32_t* n_pairs, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    GSR_TRY(check_dims(cam->width, cam->height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_pairs);
+    if (n > 0) {
+        GSR_NEED(ids); GSR_NEED(n_visible); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities);
+    }
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::tile_ws_bytes(n, 0, cam->width, cam->height)));
+    return hip_status(gsr::launch_tile_prepare(*cfg, cam->width, cam->height, n, ids, n_visible,
+                                               means2d, conics, opacities, n_pairs, ws,
+                                               (hipStream_t)stream),
+                      "gs_tile_prepare");
+}
+
+int gs_tile_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* ids,
+                       const uint32_t* keys, const float* means2d, const float* conics,
+                       const float* opacities, const float* rgb, const uint32_t* n_pairs,
+                       int64_t pair_capacity, float* out_rgb, float* out_T, int32_t* n_contrib,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    GSR_TRY(check_dims(cam->width, cam->height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    if (pair_capacity < 0 || pair_capacity > (int64_t)1 << 31)
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside 0..2^31");
+    GSR_NEED(n_pairs); GSR_NEED(out_rgb); GSR_NEED(out_T); GSR_NEED(n_contrib);
+    if (n > 0) {
+        GSR_NEED(ids); GSR_NEED(keys); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities);
+        GSR_NEED(rgb);
+    }
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::tile_ws_bytes(n, (size_t)pair_capacity, cam->width, cam->height)));
+    return hip_status(gsr::launch_tile_fwd(*cfg, cam->width, cam->height, n, ids, keys, means2d,
+                                           conics, opacities, rgb, n_pairs, (size_t)pair_capacity,
+                                           out_rgb, out_T, n_contrib, ws, (hipStream_t)stream),
+                      "gs_tile_raster_fwd");
+}
+
+int gs_tile_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const float* means2d,
+                       const float* conics, const float* opacities, const float* rgb,
+                       const float* dL_dimage, const float* T_final, const int32_t* n_contrib,
+                       int64_t pair_capacity, float* dL_dmeans2d, float* dL_dconics,
+                       float* dL_dopacities, float* dL_drgb, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    GSR_TRY(check_dims(cam->width, cam->height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    if (pair_capacity < 0 || pair_capacity > (int64_t)1 << 31)
+        return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside 0..2^31");
+    GSR_NEED(dL_dimage); GSR_NEED(T_final); GSR_NEED(n_contrib);
+    if (n > 0) {
+        GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
+        GSR_NEED(dL_dmeans2d); GSR_NEED(dL_dconics); GSR_NEED(dL_dopacities); GSR_NEED(dL_drgb);
+    }
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::tile_ws_bytes(n, (size_t)pair_capacity, cam->width, cam->height)));
+    return hip_status(gsr::launch_tile_bwd(*cfg, cam->width, cam->height, n, means2d, conics,
+                                           opacities, rgb, dL_dimage, T_final, n_contrib,
+                                           (size_t)pair_capacity, dL_dmeans2d, dL_dconics,
+                                           dL_dopacities, dL_drgb, ws, (hipStream_t)stream),
+                      "gs_tile_raster_bwd");
+}
+
 }  // extern "C"

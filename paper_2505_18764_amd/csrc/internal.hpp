@@ -63,6 +63,8 @@ hipError_t launch_sort_u32(int n, uint32_t* keys, int32_t* vals, const int32_t* 
 hipError_t launch_sort_u64(int n, uint64_t* keys, int32_t* vals, const int32_t* n_dev,
                            int end_bit, void* ws, hipStream_t s);
 hipError_t launch_fill_u32(void* p, size_t count, uint32_t value, hipStream_t s);
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t count, uint32_t* sums,
+                                 hipStream_t s);
 hipError_t launch_compact(int n, const uint32_t* key_by_id, uint32_t* keys, int32_t* ids,
                           int32_t* n_visible, void* ws, hipStream_t s);
 hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
@@ -76,5 +78,23 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                              const float* rgb, const void* fb, const float* dL_dimg,
                              float* g_means2d, float* g_conics, float* g_opac, float* g_rgb,
                              int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s);
+
+
+// ---- tile-based comparison rasterizer ------------------------------------------------------
+size_t tile_ws_bytes(int n, size_t cap, int W, int H);
+hipError_t launch_tile_prepare(const gs_config& cfg, int W, int H, int n, const int32_t* ids,
+                               const int32_t* n_visible, const float* means2d,
+                               const float* conics, const float* opac, uint32_t* n_pairs,
+                               void* ws, hipStream_t s);
+hipError_t launch_tile_fwd(const gs_config& cfg, int W, int H, int n, const int32_t* ids,
+                           const uint32_t* keys, const float* means2d, const float* conics,
+                           const float* opac, const float* rgb, const uint32_t* n_pairs,
+                           size_t cap, float* out_rgb, float* out_T, int32_t* n_contrib, void* ws,
+                           hipStream_t s);
+hipError_t launch_tile_bwd(const gs_config& cfg, int W, int H, int n, const float* means2d,
+                           const float* conics, const float* opac, const float* rgb,
+                           const float* dL_dimg, const float* T_final, const int32_t* n_contrib,
+                           size_t cap, float* g_m, float* g_c, float* g_o, float* g_rgb, void* ws,
+                           hipStream_t s);
 
 }  // namespace gsr

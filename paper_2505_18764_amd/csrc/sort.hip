@@ -110,8 +110,9 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
         }
 }
 
-static hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, size_t count, uint32_t* sums,
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t count, uint32_t* sums,
                                  hipStream_t s) {
+    if (count == 0) return hipSuccess;
     const int blocks = (int)((count + SCAN_ITEMS - 1) / SCAN_ITEMS);
     hipLaunchKernelGGL(k_scan_sums, dim3(blocks), dim3(256), 0, s, in, count, sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, blocks);
@@ -244,7 +245,7 @@ hipError_t launch_compact(int n, const uint32_t* key_by_id, uint32_t* keys, int3
     uint32_t* offs = (uint32_t*)p; p += align_up((size_t)(nb + 1) * 4);
     uint32_t* sums = (uint32_t*)p;
     hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(SORT_THREADS), 0, s, key_by_id, n, cnt);
-    hipError_t e = exclusive_scan(cnt, offs, (size_t)nb, sums, s);
+    hipError_t e = launch_exclusive_scan(cnt, offs, (size_t)nb, sums, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(SORT_THREADS), 0, s, key_by_id, n, nb,
                        cnt, offs, keys, ids, n_visible);
@@ -280,7 +281,7 @@ static hipError_t sort_pairs(int n, K* keys, int32_t* vals, const int32_t* n_dev
     for (int shift = 0; shift < end_bit; shift += 8, ++passes) {
         hipLaunchKernelGGL(k_sort_hist<K>, dim3(nb), dim3(SORT_THREADS), 0, s, kin, n, n_dev,
                            shift, nb, hist);
-        hipError_t e = exclusive_scan(hist, offs, table, sums, s);
+        hipError_t e = launch_exclusive_scan(hist, offs, table, sums, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_sort_scatter<K>, dim3(nb), dim3(SORT_THREADS), 0, s, kin, vin, kout,
                            vout, n, n_dev, shift, nb, offs);

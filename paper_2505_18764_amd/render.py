@@ -87,10 +87,14 @@ class Workspace:
         self.device = torch.device(device)
         self.buf = None
 
-    def get(self, nbytes: int):
+    def get(self, nbytes: int, keep: bool = False):
+        """A buffer of at least nbytes; with keep, a grown buffer starts with the old contents."""
         nbytes = max(int(nbytes), 256)
         if self.buf is None or self.buf.numel() < nbytes:
-            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            new = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            if keep and self.buf is not None:
+                new[: self.buf.numel()].copy_(self.buf)
+            self.buf = new
         return self.buf
 
     @property
@@ -306,3 +310,43 @@ def rasterize_2d(means2d, conics, opacities, rgb, depth, width, height, cfg=None
     cfg = cfg or RasterConfig()
     ws = ws or Workspace(means2d.device)
     return Raster2DFn.apply(means2d, conics, opacities, rgb, depth, width, height, cfg, ws)
+
+
+# ---- tile-based comparison rasterizer --------------------------------------------------------
+
+def tile_forward(p: Projected, cfg: RasterConfig, ws: Workspace, out=None):
+    """gs_tile_prepare, host readback of the pair count (the dynamic allocation), then
+    gs_tile_raster_fwd. Returns dict(image, T, n_contrib, n_pairs, capacity)."""
+    dev = p.means2d.device
+    W, H, n = p.width, p.height, p.n
+    cc, cm = cfg.c(), image_camera(W, H)
+    st = _stream(dev)
+    n_pairs = torch.zeros(1, dtype=torch.int32, device=dev)
+    b = ws.get(L.gs_tile_workspace_size(n, 0, W, H))
+    L.gs_tile_prepare(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, n_pairs, b,
+                      b.numel(), st)
+    npairs = int(n_pairs.item())
+    cap = max(npairs, 1)
+    b = ws.get(L.gs_tile_workspace_size(n, cap, W, H), keep=True)
+    if out is None:
+        out = dict(image=torch.empty(3, H, W, device=dev), T=torch.empty(H, W, device=dev),
+                   n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
+    L.gs_tile_raster_fwd(cm, cc, n, p.ids, p.keys, p.means2d, p.conics, p.opacities, p.rgb,
+                         n_pairs, cap, out["image"], out["T"], out["n_contrib"], b, b.numel(), st)
+    out.update(n_pairs=npairs, capacity=cap)
+    return out
+
+
+def tile_backward(p: Projected, fwd: dict, dL_dimage, cfg: RasterConfig, ws: Workspace, out=None):
+    """gs_tile_raster_bwd with the workspace the forward filled."""
+    dev = p.means2d.device
+    W, H, n = p.width, p.height, p.n
+    cc, cm = cfg.c(), image_camera(W, H)
+    if out is None:
+        out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
+                   opacities=torch.empty(n, device=dev), rgb=torch.empty(n, 3, device=dev))
+    b = ws.get(L.gs_tile_workspace_size(n, fwd["capacity"], W, H), keep=True)
+    L.gs_tile_raster_bwd(cm, cc, n, p.means2d, p.conics, p.opacities, p.rgb, _c32(dL_dimage),
+                         fwd["T"], fwd["n_contrib"], fwd["capacity"], out["means2d"],
+                         out["conics"], out["opacities"], out["rgb"], b, b.numel(), _stream(dev))
+    return out
