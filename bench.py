@@ -41,6 +41,8 @@ def _parse():
     ap.add_argument("--cpu-blocks", type=int, default=12)
     ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-based baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -73,6 +75,17 @@ def main():
     import torch
     import synth
     from paper_2505_18764_amd import render as R
+
+    if args.copy_probe:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel(), "copies": 3}))
+        return
 
     dev = torch.device("cuda:0")
     c3 = dict(synth.CFG3)

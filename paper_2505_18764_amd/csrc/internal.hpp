@@ -35,6 +35,8 @@ struct RasterWs {
     unsigned long long* counters;  // [16] stats scratch
     uint32_t* weights; // [tiles] sampled splat count per tile
     int32_t* order;    // [tiles] tiles by decreasing weight
+    uint32_t* bits;    // [tiles][wpr] occupancy bitmap: one bit per 64 sorted splats
+    int wpr;           // words per bitmap row (0: no bitmap)
 };
 size_t raster_ws_bytes(int n, int width, int height, bool bwd);
 RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd);

@@ -39,7 +39,9 @@ static_assert(sizeof(Rec) == REC_BYTES, "record size");
 
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr int WEIGHT_SAMPLE = 8;        // every 8th sorted splat votes for the tiles it touches
-constexpr int MAX_ORDERED_TILES = 4096; // tiles ordered by weight in one workgroup (LDS sort)
+constexpr int CHUNK_SPLATS = 64;        // sorted splats per bit of the tile occupancy bitmap
+constexpr size_t BITMAP_BUDGET = 256u << 20;  // the bitmap is skipped above this many bytes
+constexpr int MAX_ORDERED_TILES = 8192; // tiles ordered by weight in one workgroup (LDS sort)
 
 // Tile schedule. The work of a tile grows with the number of splats over it, which on clustered
 // scenes varies by orders of magnitude across the screen. Workgroups are dispatched in block
@@ -85,60 +87,90 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
-// ---- setup: records and tile rectangles in sorted order --------------------------------------
+// ---- setup: records, tile rectangles, occupancy bitmap and tile weights ---------------------
+// One workgroup per SETUP_SPAN consecutive sorted positions = one 32-bit column of the bitmap
+// (32 chunks of 64 splats). The workgroup gathers, in LDS, one word of chunk bits and one splat
+// count per tile, then writes its bitmap column with plain stores and adds its counts to the tile
+// weights: one global atomic per (workgroup, touched tile), none contended within an instruction.
+constexpr int SETUP_SPAN = 32 * CHUNK_SPLATS;   // 2048 sorted positions per workgroup
+constexpr int MAX_LDS_TILES = 8192;
+
 __global__ __launch_bounds__(256) void k_raster_setup(
     int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
     const float* __restrict__ means2d, const float* __restrict__ conics,
     const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
-    int saturate, int tiles_x, Rec* __restrict__ rec, uint2* __restrict__ rect,
-    uint32_t* __restrict__ weights) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    int saturate, int tiles_x, int ntiles, Rec* __restrict__ rec, uint2* __restrict__ rect,
+    uint32_t* __restrict__ weights, uint32_t* __restrict__ bits, int wpr) {
+    __shared__ uint32_t s_bits[MAX_LDS_TILES];
+    __shared__ uint32_t s_cnt[MAX_LDS_TILES];
+    const bool in_lds = ntiles <= MAX_LDS_TILES;
+    if (in_lds)
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) { s_bits[t] = 0u; s_cnt[t] = 0u; }
+    __syncthreads();
     int nvis = *nvis_ptr;
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
-    uint2 rr = make_uint2(0xFFFFu, 0u);   // matches no tile
-    if (p < nvis) {
-        const int id = sorted_ids[p];
-        if ((unsigned)id < (unsigned)n) {
-            const float mx = means2d[2 * (size_t)id], my = means2d[2 * (size_t)id + 1];
-            const float a = conics[3 * (size_t)id], b = conics[3 * (size_t)id + 1],
-                        c = conics[3 * (size_t)id + 2];
-            const float o = opac[id];
-            float cr = rgb[3 * (size_t)id], cg = rgb[3 * (size_t)id + 1], cb = rgb[3 * (size_t)id + 2];
-            if (saturate) { cr = fminf(cr, 1.f); cg = fminf(cg, 1.f); cb = fminf(cb, 1.f); }
-            const float det = a * c - b * b;
-            if (a > 0.f && c > 0.f && det > 0.f && o >= amin && isfinite(mx) && isfinite(my)) {
-                // alpha >= alpha_min  <=>  q <= r2 = 2 ln(o / alpha_min): the ellipse's half
-                // extents are sqrt(r2 Sigma_xx), sqrt(r2 Sigma_yy) with Sigma = conic^-1;
-                // padded so FP32 rounding never puts a passing pixel outside the box.
-                const float r2 = 2.0f * logf(o / amin);
-                const float hx = sqrtf(fmaxf(r2 * c / det, 0.f)) * 1.001f + 0.01f;
-                const float hy = sqrtf(fmaxf(r2 * a / det, 0.f)) * 1.001f + 0.01f;
-                const float lim = 32768.f;
-                const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
-                const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), fminf((float)W, lim));
-                const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
-                const float fy1 = fminf(fmaxf(floorf(my + hy - 0.5f) + 1.f, 0.f), fminf((float)H, lim));
-                if (fx0 < fx1 && fy0 < fy1) {
-                    const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
-                    const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
-                    Rec r;
-                    r.a = make_float4(mx, my, -0.5f * LOG2E * a, -LOG2E * b);
-                    r.b = make_float4(-0.5f * LOG2E * c, o, cr, cg);
-                    r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, x0 | (x1 << 16), y0 | (y1 << 16));
-                    rec[p] = r;
-                    const uint32_t tx0 = x0 / TILE, tx1 = (x1 - 1) / TILE;
-                    const uint32_t ty0 = y0 / TILE, ty1 = (y1 - 1) / TILE;
-                    rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-                    if (p % WEIGHT_SAMPLE == 0 && (tx1 - tx0 + 1) * (ty1 - ty0 + 1) <= 64)
+    const int p0 = blockIdx.x * SETUP_SPAN;
+    for (int j = 0; j < SETUP_SPAN / 256; ++j) {
+        const int p = p0 + j * 256 + threadIdx.x;
+        if (p >= n) break;
+        uint2 rr = make_uint2(0xFFFFu, 0u);   // matches no tile
+        if (p < nvis) {
+            const int id = sorted_ids[p];
+            if ((unsigned)id < (unsigned)n) {
+                const float mx = means2d[2 * (size_t)id], my = means2d[2 * (size_t)id + 1];
+                const float a = conics[3 * (size_t)id], b = conics[3 * (size_t)id + 1],
+                            c = conics[3 * (size_t)id + 2];
+                const float o = opac[id];
+                float cr = rgb[3 * (size_t)id], cg = rgb[3 * (size_t)id + 1],
+                      cb = rgb[3 * (size_t)id + 2];
+                if (saturate) { cr = fminf(cr, 1.f); cg = fminf(cg, 1.f); cb = fminf(cb, 1.f); }
+                const float det = a * c - b * b;
+                if (a > 0.f && c > 0.f && det > 0.f && o >= amin && isfinite(mx) && isfinite(my)) {
+                    // alpha >= alpha_min  <=>  q <= r2 = 2 ln(o / alpha_min): the ellipse's half
+                    // extents are sqrt(r2 Sigma_xx), sqrt(r2 Sigma_yy) with Sigma = conic^-1;
+                    // padded so FP32 rounding never puts a passing pixel outside the box.
+                    const float r2 = 2.0f * logf(o / amin);
+                    const float hx = sqrtf(fmaxf(r2 * c / det, 0.f)) * 1.001f + 0.01f;
+                    const float hy = sqrtf(fmaxf(r2 * a / det, 0.f)) * 1.001f + 0.01f;
+                    const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
+                    const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), (float)W);
+                    const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
+                    const float fy1 = fminf(fmaxf(floorf(my + hy - 0.5f) + 1.f, 0.f), (float)H);
+                    if (fx0 < fx1 && fy0 < fy1) {
+                        const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
+                        const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
+                        Rec r;
+                        r.a = make_float4(mx, my, -0.5f * LOG2E * a, -LOG2E * b);
+                        r.b = make_float4(-0.5f * LOG2E * c, o, cr, cg);
+                        r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, x0 | (x1 << 16),
+                                         y0 | (y1 << 16));
+                        rec[p] = r;
+                        const uint32_t tx0 = x0 / TILE, tx1 = (x1 - 1) / TILE;
+                        const uint32_t ty0 = y0 / TILE, ty1 = (y1 - 1) / TILE;
+                        rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                        const uint32_t bit = 1u << ((uint32_t)(p - p0) / CHUNK_SPLATS);
                         for (uint32_t ty = ty0; ty <= ty1; ++ty)
-                            for (uint32_t tx = tx0; tx <= tx1; ++tx)
-                                atomicAdd(&weights[ty * (uint32_t)tiles_x + tx], 1u);
+                            for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+                                const uint32_t t = ty * (uint32_t)tiles_x + tx;
+                                if (in_lds) {
+                                    atomicOr(&s_bits[t], bit);
+                                    atomicAdd(&s_cnt[t], 1u);
+                                } else if (p % WEIGHT_SAMPLE == 0) {
+                                    atomicAdd(&weights[t], 1u);
+                                }
+                            }
+                    }
                 }
             }
         }
+        rect[p] = rr;
     }
-    rect[p] = rr;
+    __syncthreads();
+    if (in_lds)
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+            if (wpr > 0) bits[(size_t)t * wpr + blockIdx.x] = s_bits[t];
+            if (s_cnt[t]) atomicAdd(&weights[t], s_cnt[t]);
+        }
 }
 
 // ---- the shared walk: scan 4096 sorted splats, compact hits in order, stage records ----------
@@ -149,32 +181,42 @@ struct Walk {
     Rec rec[BATCH];
 };
 
-// Tests the wave's 1024 splats of this fill against the tile; writes the in-order offsets of the
-// hits to w.seg[wave] and their count to w.segn[wave].
+// Tests the wave's 1024 splats of this fill against the tile, one 64-splat chunk per set bit of
+// `chunks` (16 bits, from the occupancy bitmap); writes the in-order offsets of the hits to
+// w.seg[wave] and their count to w.segn[wave].
 __device__ __forceinline__ void scan_span(Walk& w, const uint2* __restrict__ rect, int wb, int nvis,
                                           uint32_t ttx, uint32_t tty, int wave, int lane,
-                                          uint64_t lt) {
+                                          uint64_t lt, uint32_t chunks) {
     int cnt = 0;
-    if (wb < nvis) {
-        const int lim = min(SPAN, nvis - wb);
-#pragma unroll 4
-        for (int it0 = 0; it0 < SPAN / 64; it0 += 4) {
-            uint2 r[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int o = (it0 + u) * 64 + lane;
-                r[u] = o < lim ? rect[wb + o] : make_uint2(0xFFFFu, 0u);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool hit = rect_hit(r[u], ttx, tty);
-                const uint64_t m = ballot(hit);
-                if (hit) w.seg[wave][cnt + popc(m & lt)] = (uint16_t)((it0 + u) * 64 + lane);
-                cnt += popc(m);
-            }
-        }
+    if (wb >= nvis) chunks = 0;
+    while (chunks) {
+        const int b0 = __builtin_ctz(chunks);
+        chunks &= chunks - 1u;
+        const int b1 = chunks ? __builtin_ctz(chunks) : -1;   // two chunks per round
+        if (b1 >= 0) chunks &= chunks - 1u;
+        const int o0 = b0 * 64 + lane, o1 = b1 * 64 + lane;
+        const uint2 r0 = wb + o0 < nvis ? rect[wb + o0] : make_uint2(0xFFFFu, 0u);
+        const uint2 r1 = (b1 >= 0 && wb + o1 < nvis) ? rect[wb + o1] : make_uint2(0xFFFFu, 0u);
+        const bool h0 = rect_hit(r0, ttx, tty);
+        const uint64_t m0 = ballot(h0);
+        if (h0) w.seg[wave][cnt + popc(m0 & lt)] = (uint16_t)o0;
+        cnt += popc(m0);
+        const bool h1 = rect_hit(r1, ttx, tty);
+        const uint64_t m1 = ballot(h1);
+        if (h1) w.seg[wave][cnt + popc(m1 & lt)] = (uint16_t)o1;
+        cnt += popc(m1);
     }
     if (lane == 0) w.segn[wave] = cnt;
+}
+
+// The tile's 64 chunk bits for the fill starting at sorted position `base` (all ones without a
+// bitmap).
+__device__ __forceinline__ uint64_t window_bits(const uint32_t* __restrict__ trow, int wpr, int base) {
+    if (!trow) return ~0ull;
+    const int wi = (base / CHUNK) * 2;
+    const uint32_t lo = wi < wpr ? trow[wi] : 0u;
+    const uint32_t hi = wi + 1 < wpr ? trow[wi + 1] : 0u;
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // Stages hits [b0, b0 + BATCH) of the fill (in order across the four waves' segments).
@@ -198,7 +240,8 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
 template <int RFMT, bool TCULL, bool INSTR>
 __global__ __launch_bounds__(NT) void k_raster_fwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
-    const uint2* __restrict__ rect, const int32_t* __restrict__ order, int W, int H, int tiles_x,
+    const uint2* __restrict__ rect, const int32_t* __restrict__ order,
+    const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x,
     float amin, float amax, float tmin, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
     float* __restrict__ out_T, int32_t* __restrict__ out_cov,
     unsigned long long* __restrict__ stats) {
@@ -231,8 +274,12 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     uint32_t nq = 0;
 
+    const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
     for (int base = 0; base < nvis; base += CHUNK) {
-        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt);
+        const uint64_t wbits = window_bits(trow, wpr, base);
+        if (wbits == 0) continue;                 // no splat of this fill touches the tile
+        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt,
+                  (uint32_t)(wbits >> (16 * wave)) & 0xFFFFu);
         __syncthreads();
         const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
         if (INSTR) nq += total;
@@ -373,7 +420,8 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
 template <int RFMT, bool INSTR>
 __global__ __launch_bounds__(NT) void k_raster_bwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
-    const uint2* __restrict__ rect, const int32_t* __restrict__ order, int W, int H, int tiles_x,
+    const uint2* __restrict__ rect, const int32_t* __restrict__ order,
+    const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x,
     float amin, float amax, float tmin, int fb_fmt, const void* __restrict__ fb,
     const float* __restrict__ dL_dimg,
     int mode, int X, float* __restrict__ grad, int32_t* __restrict__ out_live,
@@ -419,8 +467,12 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     uint32_t nq = 0;
     const bool lane_acc = (mode == GS_REDUCE_HYBRID_LANE);
 
+    const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
     for (int base = 0; base < nvis; base += CHUNK) {
-        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt);
+        const uint64_t wbits = window_bits(trow, wpr, base);
+        if (wbits == 0) continue;                 // no splat of this fill touches the tile
+        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt,
+                  (uint32_t)(wbits >> (16 * wave)) & 0xFFFFu);
         __syncthreads();
         const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
         if (INSTR) nq += total;
@@ -578,10 +630,17 @@ static int tiles_of(int width, int height) {
     return ((width + TILE - 1) / TILE) * ((height + TILE - 1) / TILE);
 }
 
+// Words per tile row of the occupancy bitmap (0: no bitmap, every chunk is tested).
+static int bitmap_wpr(int n, int width, int height) {
+    const size_t nt = (size_t)tiles_of(width, height);
+    const size_t wpr = ((size_t)n + SETUP_SPAN - 1) / SETUP_SPAN;   // one word per setup block
+    return (n > 0 && nt <= (size_t)MAX_LDS_TILES && nt * wpr * 4 <= BITMAP_BUDGET) ? (int)wpr : 0;
+}
+
 size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
     const size_t nt = (size_t)tiles_of(width, height);
     size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up(16 * 8) +
-               align_up(nt * 4) * 2;
+               align_up(nt * 4) * 2 + align_up(nt * (size_t)bitmap_wpr(n, width, height) * 4);
     if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4);
     return b;
 }
@@ -595,6 +654,8 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     r.counters = (unsigned long long*)p; p += align_up(16 * 8);
     r.weights = (uint32_t*)p; p += align_up(nt * 4);
     r.order = (int32_t*)p;    p += align_up(nt * 4);
+    r.wpr = bitmap_wpr(n, width, height);
+    r.bits = (uint32_t*)p;    p += align_up(nt * (size_t)r.wpr * 4);
     r.grad = bwd ? (float*)p : nullptr;
     return r;
 }
@@ -610,9 +671,10 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
     if (e != hipSuccess) return e;
     if (n > 0) {
         const int sat = (cfg.fb_format == FB_UNORM16 || cfg.fb_format == FB_UNORM8) ? 1 : 0;
-        hipLaunchKernelGGL(k_raster_setup, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
-                           n_visible, means2d, conics, opac, rgb, width, height, cfg.alpha_min,
-                           sat, tiles_x, (Rec*)r.rec, (uint2*)r.rect, r.weights);
+        hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN), dim3(256), 0, s,
+                           n, sorted_ids, n_visible, means2d, conics, opac, rgb, width, height,
+                           cfg.alpha_min, sat, tiles_x, ntiles, (Rec*)r.rec, (uint2*)r.rect,
+                           r.weights, r.bits, r.wpr);
     }
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, r.weights, ntiles, r.order);
     return hipGetLastError();
@@ -622,9 +684,9 @@ static bool saturating(int fmt) { return fmt == FB_UNORM16 || fmt == FB_UNORM8; 
 
 template <bool TC, bool IN>
 static void fwd_by_fmt(int rfmt, void (*&k)(int, const int32_t*, const Rec*, const uint2*,
-                                             const int32_t*, int, int, int, float, float, float, int,
-                                             void*, float*, float*, int32_t*,
-                                             unsigned long long*)) {
+                                             const int32_t*, const uint32_t*, int, int, int, int,
+                                             float, float, float, int, void*, float*, float*,
+                                             int32_t*, unsigned long long*)) {
     switch (rfmt) {
     case FB_F32: k = k_raster_fwd<FB_F32, TC, IN>; break;
     case FB_F16: k = k_raster_fwd<FB_F16, TC, IN>; break;
@@ -649,12 +711,14 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool tcull = cfg.t_min_fwd > 0.f;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_cov;
-    void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, int, int, int, float,
-              float, float, int, void*, float*, float*, int32_t*, unsigned long long*) = nullptr;
+    void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
+              int, int, int, float, float, float, int, void*, float*, float*, int32_t*,
+              unsigned long long*) = nullptr;
     if (tcull) { if (instr) fwd_by_fmt<true, true>(rfmt, k); else fwd_by_fmt<true, false>(rfmt, k); }
     else { if (instr) fwd_by_fmt<false, true>(rfmt, k); else fwd_by_fmt<false, false>(rfmt, k); }
     hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
-                       (const uint2*)r.rect, (const int32_t*)r.order, width, height, tiles_x,
+                       (const uint2*)r.rect, (const int32_t*)r.order, (const uint32_t*)r.bits,
+                       r.wpr, width, height, tiles_x,
                        cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.fb_format, fb, out_rgb, out_T,
                        out_cov,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
@@ -680,9 +744,9 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     const int nblocks = tiles_of(width, height);
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_live;
-    void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, int, int, int, float,
-              float, float, int, const void*, const float*, int, int, float*, int32_t*,
-              unsigned long long*) = nullptr;
+    void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
+              int, int, int, float, float, float, int, const void*, const float*, int, int, float*,
+              int32_t*, unsigned long long*) = nullptr;
 #define GSR_BWD_PICK(IN)                                             \
     switch (rfmt) {                                                  \
     case FB_F32: k = k_raster_bwd<FB_F32, IN>; break;                \
@@ -695,7 +759,8 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     if (instr) { GSR_BWD_PICK(true) } else { GSR_BWD_PICK(false) }
 #undef GSR_BWD_PICK
     hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
-                       (const uint2*)r.rect, (const int32_t*)r.order, width, height, tiles_x,
+                       (const uint2*)r.rect, (const int32_t*)r.order, (const uint32_t*)r.bits,
+                       r.wpr, width, height, tiles_x,
                        cfg.alpha_min, cfg.alpha_max, cfg.t_min_bwd, cfg.fb_format, fb, dL_dimg,
                        cfg.reduce_mode,
                        cfg.reduce_threshold, r.grad, out_live,
