@@ -41,6 +41,8 @@ def _parse():
     ap.add_argument("--cpu-blocks", type=int, default=12)
     ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-based baseline")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests of the serving run (0: skip); 100 more are warmup")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -212,6 +214,10 @@ def main():
         extra["fwd_tcull_ms_per_view"] = r["ms_per_view"]
         extra["fwd_tcull_stages_ms"] = r["stages_ms"]
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_run(args.serve_requests, dev)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sc, cam, G, args.cpu_blocks)
@@ -249,10 +255,26 @@ def main():
         "roofline_kernels": roof,
         "workspace_bytes": head["ws_bytes"],
         "tile_baseline": tile,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     line.update(extra)
     print(json.dumps(line), flush=True)
+
+
+def serving_run(n_requests, dev, warmup=100, rate=200.0):
+    """Continuous-batching server on 16 resident scenes (50k-3M Gaussians), resolutions
+    640x480-1920x1080, Poisson arrivals at `rate`/s, 70 % FWD / 30 % FWD_BWD, FP16 framebuffer,
+    64 GB pool, 4 streams."""
+    import synth
+    from paper_2505_18764_amd import serve as S
+    scenes = S.load_scenes(dev)
+    ex = S.GpuExecutor(scenes, S.serving_cameras(synth.CFG5_RESOLUTIONS))
+    srv = S.Server(ex, 64 << 30, slots=4).start()
+    summ = S.run_load(srv, synth.serving_requests(n_requests + warmup, rate), warmup)
+    srv.stop()
+    summ.update(offered_rate_per_s=rate, requests=n_requests, warmup=warmup)
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
 
 
 def cpu_baseline(sc, cam, G, blocks):

@@ -195,14 +195,14 @@ def preprocess_vjp(scene, cam, g_means2d, g_conics, g_rgb, g_opac, cfg=None):
 
 
 def render_scene(scene, cam, dL_dimg=None, crop=None, cfg=None):
-    """Whole oracle pipeline on a 3D scene: FP64 projection, stable depth order, FP64 raster.
-    The raster reads the projection's outputs rounded to FP32 (the raster's input precision)."""
+    """Whole oracle pipeline on a 3D scene in FP64: projection, stable depth order (by the fp32
+    depth key), raster. No intermediate is rounded, so the chain is smooth for finite
+    differences."""
     cfg = cfg or OracleConfig()
     pre = preprocess(scene, cam, cfg)
     order = visible_order(pre["keys"])
-    out = raster(pre["means2d"].astype(np.float32), pre["conic"].astype(np.float32),
-                 scene.opacities, pre["rgb"].astype(np.float32), order, cam.width, cam.height,
-                 crop=crop, dL_dimg=dL_dimg, cfg=cfg)
+    out = raster(pre["means2d"], pre["conic"], np.asarray(scene.opacities, np.float64),
+                 pre["rgb"], order, cam.width, cam.height, crop=crop, dL_dimg=dL_dimg, cfg=cfg)
     out["pre"] = pre
     out["order"] = order
     return out

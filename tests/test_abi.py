@@ -1,0 +1,119 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function include/gsr.h
+declares, reports the paper's defaults, sizes its buffers by closed forms, and rejects invalid
+arguments on the host before any HIP call (so these calls never touch a device)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsr.h")
+LIB = os.path.join(ROOT, "paper_2505_18764_amd", "libgsr.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libgsr.so not built")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_2505_18764_amd import _lib as L
+    names = _declared()
+    assert len(names) >= 14
+    cdll = ctypes.CDLL(LIB)
+    for nm in names:
+        assert hasattr(cdll, nm), nm
+    assert set(names) == set(L.exported_symbols())    # the binding covers the same names
+
+
+def test_defaults_are_the_papers_constants():
+    from paper_2505_18764_amd import _lib as L
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
+    c = L.gs_config_default()
+    assert c.alpha_min == pytest.approx(g["alpha_min"]["value"], rel=1e-7)
+    assert c.t_min_bwd == pytest.approx(g["t_min_bwd"]["value"], rel=1e-6)
+    assert c.reduce_threshold == g["reduce_threshold_hybrid"]["value"]
+    assert c.t_min_fwd == 0.0 and c.reduce_mode == L.REDUCE_MODES["hybrid"]
+    assert L.gs_version() == 1
+
+
+def test_sizes_are_closed_forms():
+    from paper_2505_18764_amd import _lib as L
+    c = L.gs_config_default()
+    assert L.gs_framebuffer_size(100, 70, "f32") == 100 * 70 * 16
+    assert L.gs_framebuffer_size(100, 70, "f16") == 100 * 70 * 8
+    assert L.gs_framebuffer_size(100, 70, "unorm8") == 100 * 70 * 4
+    assert L.gs_framebuffer_size(0, 70, "f16") == 0
+    for op in ("preprocess", "sort", "raster_fwd", "raster_bwd", "all"):
+        prev = -1
+        for n in (0, 1, 1000, 200_000, 1_000_000, 3_000_000):
+            v = L.gs_workspace_size(op, n, 1600, 1064, c)
+            assert v >= prev
+            prev = v
+        a = L.gs_workspace_size(op, 10_000, 640, 480, c)
+        b = L.gs_workspace_size(op, 10_000, 1920, 1080, c)
+        assert b >= a
+    allb = L.gs_workspace_size("all", 1_000_000, 1600, 1064, c)
+    for op in ("preprocess", "sort", "raster_fwd", "raster_bwd"):
+        assert L.gs_workspace_size(op, 1_000_000, 1600, 1064, c) <= allb
+    assert L.gs_workspace_size("raster_fwd", -1, 10, 10, c) == 0
+    assert L.gs_workspace_size("raster_fwd", 10, 0, 10, c) == 0
+    # fixed O(N + pixels) memory at the 1M / 1600x1064 view: well under 200 MB
+    assert allb < 200 << 20
+    assert L.gs_tile_workspace_size(1000, 5000, 128, 128) > L.gs_tile_workspace_size(1000, 0, 128, 128)
+
+
+def _cam(L, w=64, h=48):
+    c = L.GsCamera()
+    c.viewmat[0] = c.viewmat[5] = c.viewmat[10] = 1.0
+    c.fx = c.fy = 50.0
+    c.cx, c.cy, c.width, c.height, c.znear = w / 2, h / 2, w, h, 0.2
+    return c
+
+
+def test_invalid_arguments_rejected_on_host():
+    from paper_2505_18764_amd import _lib as L
+    cfg = L.gs_config_default()
+    cam = _cam(L)
+    fake = 0x1000    # never dereferenced: validation fails first
+    buf = (ctypes.c_char * 4096)()
+    ws = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 256
+
+    def raster(cam_, cfg_, n=10, nvis=fake, fb=fake, ws_=ws, wsb=16):
+        return L.lib().gs_raster_fwd(ctypes.byref(cam_) if cam_ is not None else None,
+                                     ctypes.byref(cfg_), n, fake, nvis, fake, fake, fake, fake, fb,
+                                     None, None, None, None, ws_, wsb, None)
+
+    assert raster(None, cfg) == 1 and "camera" in L.gs_last_error()
+    bad = _cam(L, w=0)
+    assert raster(bad, cfg) == 1 and "image" in L.gs_last_error()
+    for field, val in (("fb_format", 9), ("fb_round", 5), ("reduce_mode", 11),
+                       ("reduce_threshold", 65), ("sh_degree", 4), ("flags", 8)):
+        c2 = L.gs_config_default()
+        setattr(c2, field, val)
+        assert raster(cam, c2) == 1, field
+    c2 = L.gs_config_default()
+    c2.alpha_min = 0.0
+    assert raster(cam, c2) == 1
+    c2 = L.gs_config_default()
+    c2.alpha_max = 1.5
+    assert raster(cam, c2) == 1
+    assert raster(cam, cfg, n=-3) == 1
+    assert raster(cam, cfg, nvis=None) == 1 and "n_visible" in L.gs_last_error()
+    assert raster(cam, cfg, fb=None) == 1
+    assert raster(cam, cfg, ws_=None, wsb=0) == 1
+    assert raster(cam, cfg, wsb=16) == 2 and "workspace" in L.gs_last_error()  # GS_ERR_CAPACITY
+    assert raster(cam, cfg, ws_=ws + 4, wsb=1 << 30) == 1                       # misaligned
+    assert L.lib().gs_sort(-1, None, None, fake, None, 0, None) == 1
+    assert L.lib().gs_preprocess(ctypes.byref(cam), ctypes.byref(cfg), 5, None, None, None, None,
+                                 None, None, None, None, None, None, None, fake, ws, 1 << 20,
+                                 None) == 1
+    cz = _cam(L)
+    cz.znear = 0.0
+    assert L.lib().gs_preprocess_bwd(ctypes.byref(cz), ctypes.byref(cfg), 0, *([None] * 14),
+                                     None) == 1

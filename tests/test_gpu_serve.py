@@ -1,0 +1,48 @@
+"""Serving on the GPU: requests of different scenes, sizes and modes admitted concurrently on
+several streams give the same results as each request run alone."""
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_2505_18764_amd import serve as S  # noqa: E402
+
+
+def _scenes(dev):
+    out = {}
+    for j, n in enumerate([20_000, 60_000, 150_000, 5_000]):
+        sc = synth.scene3d(n, seed=600 + j)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        out[j] = (t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh))
+    return out
+
+
+def test_results_alone_equal_results_in_the_mix():
+    dev = torch.device("cuda:0")
+    res = [(320, 240), (640, 480), (400, 300)]
+    ex = S.GpuExecutor(_scenes(dev), S.serving_cameras(res))
+    g = np.random.default_rng(3)
+    specs = [(int(g.integers(0, 4)), res[int(g.integers(0, 3))],
+              S.FWD if g.uniform() < 0.6 else S.FWD_BWD) for _ in range(24)]
+    srv = S.Server(ex, pool_bytes=8 << 30, slots=4).start()
+    mix = [srv.submit(S.Request(rid=i, scene=sc, width=W, height=H, mode=m, keep_result=True))
+           for i, (sc, (W, H), m) in enumerate(specs)]
+    for r in mix:
+        assert r.wait(120)
+    srv.stop()
+    assert all(r.status == "done" for r in mix)
+    assert srv.peak_running > 1                          # work really overlapped on the device
+    for i, (sc, (W, H), m) in enumerate(specs):
+        srv1 = S.Server(ex, pool_bytes=8 << 30, slots=1).start()
+        alone = srv1.submit(S.Request(rid=i, scene=sc, width=W, height=H, mode=m, keep_result=True))
+        assert alone.wait(120)
+        srv1.stop()
+        a, b = mix[i].result, alone.result
+        np.testing.assert_array_equal(a["image"].cpu().numpy(), b["image"].cpu().numpy())
+        if m == S.FWD_BWD:
+            for k in a["grads"]:
+                assert rel_l2(a["grads"][k].cpu().numpy(), b["grads"][k].cpu().numpy()) <= 1e-5, k
