@@ -25,11 +25,18 @@ constexpr int SPAN = 1024;         // sorted splats one wave tests per fill
 constexpr int CHUNK = 4 * SPAN;    // sorted splats the workgroup tests per fill
 constexpr int BATCH = 256;         // splat records staged in LDS at once
 
-// A staged splat: a = (mean x, mean y, a', b'); b = (c', opacity, r, g);
+// A staged splat: a = (mean x, mean y, a', k); b = (d', opacity, r, g);
 // c = (bits of colour b, sorted position, x0 | x1 << 16, y0 | y1 << 16) with the pixel bounding
-// box [x0, x1) x [y0, y1) of the alpha >= alpha_min ellipse, clamped to the image. The conic is
-// stored pre-scaled, (a', b', c') = -log2(e) (a/2, b, c/2), so that the exponent of
-// alpha = o 2^p is p = dx (a' dx + b' dy) + c' dy^2 = -q/2 log2(e).
+// box [x0, x1) x [y0, y1) of the alpha >= alpha_min ellipse, clamped to the image.
+//
+// The conic Q = [[a, b], [b, c]] is stored in its LDL^T factors: q = d^T Q d =
+// a (dx + k dy)^2 + (det Q / a) dy^2 with k = b / a, a sum of two non-negative terms. The
+// expanded form a dx^2 + 2b dx dy + c dy^2 cancels terms of size q / (1 - rho^2) (rho the
+// correlation of the footprint) down to q, which in FP32 loses several digits on long thin
+// splats, e.g. those just beyond the near plane whose projected means lie thousands of pixels
+// off-screen; the factored form costs the same instructions. k and det Q / a are formed in FP64
+// from the FP32 conic and stored pre-scaled, a' = -log2(e) a / 2 and d' = -log2(e) det Q / (2a),
+// so that the exponent of alpha = o 2^p is p = a' u^2 + d' dy^2 = -q/2 log2(e), u = dx + k dy.
 struct __align__(16) Rec {
     float4 a;
     float4 b;
@@ -124,14 +131,16 @@ __global__ __launch_bounds__(256) void k_raster_setup(
                 float cr = rgb[3 * (size_t)id], cg = rgb[3 * (size_t)id + 1],
                       cb = rgb[3 * (size_t)id + 2];
                 if (saturate) { cr = fminf(cr, 1.f); cg = fminf(cg, 1.f); cb = fminf(cb, 1.f); }
-                const float det = a * c - b * b;
-                if (a > 0.f && c > 0.f && det > 0.f && o >= amin && isfinite(mx) && isfinite(my)) {
+                // det in FP64: the products of FP32 values are exact, so its sign is exact
+                const double ad = a, bd = b, cd = c;
+                const double det = ad * cd - bd * bd;
+                if (a > 0.f && c > 0.f && det > 0.0 && o >= amin && isfinite(mx) && isfinite(my)) {
                     // alpha >= alpha_min  <=>  q <= r2 = 2 ln(o / alpha_min): the ellipse's half
                     // extents are sqrt(r2 Sigma_xx), sqrt(r2 Sigma_yy) with Sigma = conic^-1;
                     // padded so FP32 rounding never puts a passing pixel outside the box.
                     const float r2 = 2.0f * logf(o / amin);
-                    const float hx = sqrtf(fmaxf(r2 * c / det, 0.f)) * 1.001f + 0.01f;
-                    const float hy = sqrtf(fmaxf(r2 * a / det, 0.f)) * 1.001f + 0.01f;
+                    const float hx = (float)sqrt(fmax((double)r2 * cd / det, 0.0)) * 1.001f + 0.01f;
+                    const float hy = (float)sqrt(fmax((double)r2 * ad / det, 0.0)) * 1.001f + 0.01f;
                     const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
                     const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), (float)W);
                     const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
@@ -140,8 +149,9 @@ __global__ __launch_bounds__(256) void k_raster_setup(
                         const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
                         const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
                         Rec r;
-                        r.a = make_float4(mx, my, -0.5f * LOG2E * a, -LOG2E * b);
-                        r.b = make_float4(-0.5f * LOG2E * c, o, cr, cg);
+                        const double l2e = 1.4426950408889634;
+                        r.a = make_float4(mx, my, -0.5f * LOG2E * a, (float)(bd / ad));
+                        r.b = make_float4((float)(-0.5 * l2e * det / ad), o, cr, cg);
                         r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, x0 | (x1 << 16),
                                          y0 | (y1 << 16));
                         rec[p] = r;
@@ -255,7 +265,10 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     const int lx = ((qd & 3) << 1) | (lane & 1), ly = ((qd >> 2) << 1) | ((lane >> 1) & 1);
     const uint64_t lt = mask_lt(lane);
 
-    float px[4], py[4], C[4][3], T[4];
+    // C accumulates Eq. 2; with the state kept on chip, each staged batch's contributions are
+    // first summed in Cb and folded into C at the batch end, so deep pixels (thousands of
+    // fragments) take far fewer full-magnitude FP32 additions.
+    float px[4], py[4], C[4][3], Cb[4][3], T[4];
     bool valid[4];
     uint32_t nev[4], ncov[4];
     uint32_t alive = 0;
@@ -266,6 +279,7 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
         px[s] = (float)X + 0.5f;
         py[s] = (float)Y + 0.5f;
         C[s][0] = C[s][1] = C[s][2] = 0.f;
+        Cb[s][0] = Cb[s][1] = Cb[s][2] = 0.f;
         T[s] = 1.f;
         nev[s] = ncov[s] = 0;
         if (ballot(valid[s])) alive |= 1u << s;
@@ -302,15 +316,22 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
                         if (x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy &&
                             (!TCULL || ((alive >> s) & 1u))) {
                             const float dx = px[s] - A.x, dy = py[s] - A.y;
-                            const float pw = fmaf(dx, fmaf(A.z, dx, A.w * dy), B.x * dy * dy);
+                            const float u = fmaf(A.w, dy, dx);
+                            const float pw = fmaf(A.z * u, u, B.x * dy * dy);
                             const float al = fminf(amax, B.y * __builtin_amdgcn_exp2f(pw));
                             bool pass = al >= amin;
                             if (TCULL) pass = pass && T[s] >= tmin;
                             if (pass) {
                                 const float wt = al * T[s];
-                                C[s][0] = fmaf(wt, B.z, C[s][0]);
-                                C[s][1] = fmaf(wt, B.w, C[s][1]);
-                                C[s][2] = fmaf(wt, cb, C[s][2]);
+                                if constexpr (RFMT >= 0) {      // a render target stores every blend
+                                    C[s][0] = fmaf(wt, B.z, C[s][0]);
+                                    C[s][1] = fmaf(wt, B.w, C[s][1]);
+                                    C[s][2] = fmaf(wt, cb, C[s][2]);
+                                } else {
+                                    Cb[s][0] = fmaf(wt, B.z, Cb[s][0]);
+                                    Cb[s][1] = fmaf(wt, B.w, Cb[s][1]);
+                                    Cb[s][2] = fmaf(wt, cb, Cb[s][2]);
+                                }
                                 T[s] = T[s] * (1.f - al);
                                 if constexpr (RFMT >= 0) {
                                     C[s][0] = fb_round<RFMT>(C[s][0]);
@@ -326,6 +347,13 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
                             if (TCULL && !ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
                         }
                     }
+                }
+            }
+            if constexpr (RFMT < 0) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    C[s][0] += Cb[s][0]; C[s][1] += Cb[s][1]; C[s][2] += Cb[s][2];
+                    Cb[s][0] = Cb[s][1] = Cb[s][2] = 0.f;
                 }
             }
             if (TCULL && lane == 0) w.alive[wave] = (int)alive;
@@ -499,7 +527,9 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                     if (!(x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy && ((alive >> s) & 1u)))
                         continue;
                     const float dx = px[s] - A.x, dy = py[s] - A.y;
-                    const float pw = fmaf(dx, fmaf(A.z, dx, A.w * dy), B.x * dy * dy);
+                    const float u = fmaf(A.w, dy, dx);
+                    const float au = A.z * u;
+                    const float pw = fmaf(au, u, B.x * dy * dy);
                     const float e = __builtin_amdgcn_exp2f(pw);       // exp(-q/2)
                     const float araw = B.y * e;
                     const float al = fminf(amax, araw);
@@ -531,13 +561,14 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                             T[s] = fb_round<RFMT>(T[s]);
                         }
                         // bwd_diff: alpha = o exp(-q/2) (zero gradient where clamped);
-                        // dq/dmu = -2 Q d, written with the pre-scaled conic
+                        // dq/dmu = -2 Q d, in the factored form: Q d = (a u, k a u + (det/a) dy),
+                        // so dp/dd = (2 a' u, k 2 a' u + 2 d' dy) with the pre-scaled factors
                         if (araw < amax) {
                             const float gq = -0.5f * ga * araw;          // dL/dq
-                            const float gm = -ga * araw * (1.0f / LOG2E);
+                            const float gm = -2.f * ga * araw * (1.0f / LOG2E);
                             g[5] = ga * e;
-                            g[0] = gm * fmaf(2.f * A.z, dx, A.w * dy);
-                            g[1] = gm * fmaf(A.w, dx, 2.f * B.x * dy);
+                            g[0] = gm * au;
+                            g[1] = gm * fmaf(A.w, au, B.x * dy);
                             g[2] = gq * dx * dx;
                             g[3] = 2.f * gq * dx * dy;
                             g[4] = gq * dy * dy;

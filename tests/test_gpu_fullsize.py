@@ -39,8 +39,16 @@ def test_full_size_crop_and_samples(view, fmt):
     arr, order, p, W, H = view["arr"], view["order"], view["p"], view["W"], view["H"]
     crop = (W // 2 - 32, H // 2 - 32, 64, 64)        # the densest region (cluster centre)
     x0, y0, cw, ch = crop
+    ocfg = oracle.OracleConfig(beta=1e-6, beta_abs=4e-6, tau=1e-4)
+    # dL/dC is supported on the crop and zero at pixels where the oracle flags a decision the
+    # FP32 path could take the other way (the gradients of such pixels are not comparable)
+    ones = np.ones((3, H, W), np.float32)             # runs the backward loop for its T flags
+    flags = oracle.raster(arr["means2d"], arr["conics"], arr["opacities"], arr["rgb"], order, W, H,
+                          crop=crop, dL_dimg=ones, cfg=ocfg, want_grad=False)["amb"]
+    Gc = synth.image_grad(cw, ch, 303)
+    Gc[:, flags > 0] = 0.0
     G = np.zeros((3, H, W), np.float32)
-    G[:, y0:y0 + ch, x0:x0 + cw] = synth.image_grad(cw, ch, 303)
+    G[:, y0:y0 + ch, x0:x0 + cw] = Gc
     cfg = R.RasterConfig(fb_format=fmt, reduce_mode="hybrid_lane")
     ws = R.Workspace()
     st = R.new_stats("cuda")
@@ -48,7 +56,6 @@ def test_full_size_crop_and_samples(view, fmt):
     b = R.raster_backward(p, f["fb"], t(G), cfg, ws, stats=st)
     torch.cuda.synchronize()
     img = f["image"].cpu().numpy()
-    ocfg = oracle.OracleConfig(beta=1e-6, beta_abs=4e-6, tau=1e-4)
     ref = oracle.raster(arr["means2d"], arr["conics"], arr["opacities"], arr["rgb"], order, W, H,
                         crop=crop, dL_dimg=G, cfg=ocfg)
     ok = ref["amb"] == 0

@@ -1,5 +1,6 @@
 """Serving on the GPU: requests of different scenes, sizes and modes admitted concurrently on
-several streams give the same results as each request run alone."""
+several streams give the same images, bit for bit, as each request run alone, and the same
+gradients to the rounding of atomic accumulation order."""
 import numpy as np
 import pytest
 
@@ -44,5 +45,7 @@ def test_results_alone_equal_results_in_the_mix():
         a, b = mix[i].result, alone.result
         np.testing.assert_array_equal(a["image"].cpu().numpy(), b["image"].cpu().numpy())
         if m == S.FWD_BWD:
+            # gradients are summed with FP32 atomics whose order varies from run to run (also
+            # for a request run alone), so they agree to rounding only: the parity bar
             for k in a["grads"]:
-                assert rel_l2(a["grads"][k].cpu().numpy(), b["grads"][k].cpu().numpy()) <= 1e-5, k
+                assert rel_l2(a["grads"][k].cpu().numpy(), b["grads"][k].cpu().numpy()) <= 1e-4, k
