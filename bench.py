@@ -38,7 +38,7 @@ def _parse():
     ap.add_argument("--formats", default="f16,f32")
     ap.add_argument("--reduce", default="hybrid_lane")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-blocks", type=int, default=12)
+    ap.add_argument("--cpu-blocks", type=int, default=96)
     ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-based baseline")
     ap.add_argument("--serve-requests", type=int, default=600,
@@ -119,6 +119,9 @@ def main():
         stats = R.read_stats(st)
         nvis = int(p.n_visible.item())
 
+        # every call below runs on torch's current stream, which the events are recorded on; the
+        # raster_fwd / raster_bwd stages are then the k_raster_fwd launch alone and the
+        # k_raster_bwd launch between a gradient-buffer fill and the scatter to splat ids
         def step(ev=None):
             rec = (lambda i: ev[i].record()) if ev else (lambda i: None)
             rec(0)
@@ -126,27 +129,30 @@ def main():
             rec(1)
             R.sort_(q, ws)
             rec(2)
-            R.raster_forward(q, cfg, ws, fb=f["fb"], image=f["image"], T=f["T"])
+            R.raster_setup(q, cfg, ws)
             rec(3)
-            R.raster_backward(q, f["fb"], Gd, cfg, ws, out=g2)
+            R.raster_forward(q, cfg, ws, fb=f["fb"], image=f["image"], T=f["T"], reuse_setup=True)
             rec(4)
-            R.project_backward(*inp, cam, cfg, g2, out=g3)
+            R.raster_backward(q, f["fb"], Gd, cfg, ws, out=g2, reuse_setup=True)
             rec(5)
+            R.project_backward(*inp, cam, cfg, g2, out=g3)
+            rec(6)
 
+        names = ["preprocess", "sort", "raster_setup", "raster_fwd", "raster_bwd", "preprocess_bwd"]
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+               for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
             step(evs[i])
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / steps
-        names = ["preprocess", "sort", "raster_fwd", "raster_bwd", "preprocess_bwd"]
-        per = {k: float(np.median([e[j].elapsed_time(e[j + 1]) for e in evs]))
+        per = {k: float(np.mean([e[j].elapsed_time(e[j + 1]) for e in evs]))
                for j, k in enumerate(names)}
-        total = float(np.median([e[0].elapsed_time(e[5]) for e in evs]))
+        total = float(np.mean([e[0].elapsed_time(e[len(names)]) for e in evs]))
         return dict(fmt=fmt, ms_per_view=total, wall_ms_per_view=wall, stages_ms=per,
                     stats=stats, n_visible=nvis, ws_bytes=ws.nbytes)
 
@@ -283,7 +289,9 @@ def cpu_baseline(sc, cam, G, blocks):
     Gaussians, seeded choice), and the projection backward on 2 % of the Gaussians, each scaled to
     a full view."""
     import oracle
-    nth = os.cpu_count() or 1
+    # the host share of one GPU: OMP_NUM_THREADS where the launcher sets it, at most 16
+    nth = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    nth = max(1, min(nth, 16))
     cfg = oracle.OracleConfig(nthreads=nth)
     t0 = time.perf_counter()
     pre = oracle.preprocess(sc, cam, cfg)

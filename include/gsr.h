@@ -73,7 +73,10 @@ enum gs_reduce_mode {
 };
 
 enum gs_flags {
-    GS_FLAG_STATS = 1           /* count fragments, atomics and reductions into gs_stats */
+    GS_FLAG_STATS = 1,          /* count fragments, atomics and reductions into gs_stats */
+    GS_FLAG_REUSE_SETUP = 2     /* gs_raster_fwd / gs_raster_bwd: the workspace already holds the
+                                   raster setup (see gs_raster_setup) for these exact inputs,
+                                   image size, alpha_min and fb_format; skip rebuilding it */
 };
 
 /* Pinhole camera. viewmat is the 3x4 world->camera matrix [R|t], row-major; the camera looks
@@ -198,6 +201,24 @@ int gs_prepare_2d(const gs_camera* cam, const gs_config* cfg, int32_t n,
  */
 int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible,
             void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Raster setup, shared by the forward and the backward walk: per sorted position, the splat's
+ * record (mean, conic factors, opacity, colour, pixel bounding box of the alpha >= alpha_min
+ * ellipse) and its tile rectangle; per tile, an occupancy bitmap over chunks of 64 sorted splats
+ * and a splat count that orders the tiles heaviest first. gs_raster_fwd and gs_raster_bwd run it
+ * themselves unless cfg->flags has GS_FLAG_REUSE_SETUP; calling it once and passing that flag to
+ * both lets one view's forward and backward share it. The setup depends on the inputs, the image
+ * size, cfg->alpha_min and whether cfg->fb_format saturates colours; reusing a setup built for
+ * anything else gives wrong images and gradients (it cannot fault: every index is bounded).
+ * Inputs as gs_raster_fwd. Workspace: gs_workspace_size(GS_OP_RASTER_FWD, n, W, H, cfg); the
+ * backward's workspace starts with the same layout, so one buffer sized for GS_OP_RASTER_BWD
+ * serves all three calls.
+ */
+int gs_raster_setup(const gs_camera* cam, const gs_config* cfg, int32_t n,
+                    const int32_t* sorted_ids, const int32_t* n_visible,
+                    const float* means2d, const float* conics, const float* opacities,
+                    const float* rgb, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Forward rasterization (Eq. 2): for every pixel, the splats in sorted_ids[0 .. *n_visible) are

@@ -68,6 +68,8 @@ _SIGS = {
     "gs_prepare_2d": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                      c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_sort": (ctypes.c_int, [c_i, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_raster_setup": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
+                                       c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_raster_fwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                      c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
                                      c_sz, c_p]),
@@ -165,6 +167,13 @@ def gs_prepare_2d(cam: GsCamera, cfg: GsConfig, n, means2d, conics, opacities, d
 def gs_sort(n, keys, ids, n_visible, ws, ws_bytes, stream):
     _check("gs_sort", lib().gs_sort(n, _ptr(keys), _ptr(ids), _ptr(n_visible), _ptr(ws),
                                     ws_bytes, stream))
+
+
+def gs_raster_setup(cam: GsCamera, cfg: GsConfig, n, sorted_ids, n_visible, means2d, conics,
+                    opacities, rgb, ws, ws_bytes, stream):
+    _check("gs_raster_setup", lib().gs_raster_setup(
+        ctypes.byref(cam), ctypes.byref(cfg), n, _ptr(sorted_ids), _ptr(n_visible),
+        _ptr(means2d), _ptr(conics), _ptr(opacities), _ptr(rgb), _ptr(ws), ws_bytes, stream))
 
 
 def gs_raster_fwd(cam: GsCamera, cfg: GsConfig, n, sorted_ids, n_visible, means2d, conics,

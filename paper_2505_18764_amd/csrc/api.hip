@@ -85,7 +85,8 @@ int check_cfg(const gs_config* c) {
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown reduce_mode %d", c->reduce_mode);
     if (c->reduce_threshold < 0 || c->reduce_threshold > 64)
         return fail(GS_ERR_INVALID_ARGUMENT, "reduce_threshold %d outside 0..64", c->reduce_threshold);
-    if (c->flags & ~GS_FLAG_STATS) return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", c->flags);
+    if (c->flags & ~(GS_FLAG_STATS | GS_FLAG_REUSE_SETUP))
+        return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", c->flags);
     return GS_OK;
 }
 
@@ -214,6 +215,25 @@ int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible, v
     GSR_TRY(check_ws(ws, ws_bytes, gsr::sort_ws_bytes(n, 4)));
     return hip_status(gsr::launch_sort_u32(n, keys, ids, n_visible, ws, (hipStream_t)stream),
                       "gs_sort");
+}
+
+int gs_raster_setup(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* sorted_ids,
+                    const int32_t* n_visible, const float* means2d, const float* conics,
+                    const float* opacities, const float* rgb, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    GSR_TRY(check_dims(cam->width, cam->height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    if (n > 0) {
+        GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
+    }
+    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, false)));
+    return hip_status(gsr::launch_raster_setup(*cfg, cam->width, cam->height, n, sorted_ids,
+                                               n_visible, means2d, conics, opacities, rgb, ws,
+                                               (hipStream_t)stream),
+                      "gs_raster_setup");
 }
 
 int gs_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* sorted_ids,

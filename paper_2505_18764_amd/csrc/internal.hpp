@@ -69,6 +69,10 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t count
                                  hipStream_t s);
 hipError_t launch_compact(int n, const uint32_t* key_by_id, uint32_t* keys, int32_t* ids,
                           int32_t* n_visible, void* ws, hipStream_t s);
+hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int n,
+                               const int32_t* sorted_ids, const int32_t* n_visible,
+                               const float* means2d, const float* conics, const float* opac,
+                               const float* rgb, void* ws, hipStream_t s);
 hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                              const int32_t* sorted_ids, const int32_t* n_visible,
                              const float* means2d, const float* conics, const float* opac,

@@ -242,7 +242,10 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
                 if (off >= w.segn[2]) { off -= w.segn[2]; ws = 3; }
             }
         }
-        w.rec[tid] = rec[base + ws * SPAN + w.seg[ws][off]];
+        const int pos = base + ws * SPAN + w.seg[ws][off];
+        Rec r = rec[pos];
+        r.c.y = (uint32_t)pos;      // the gradient slot comes from the walk, never from memory
+        w.rec[tid] = r;
     }
 }
 
@@ -256,7 +259,8 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     float* __restrict__ out_T, int32_t* __restrict__ out_cov,
     unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
-    const int tile = order[blockIdx.x];
+    int tile = order[blockIdx.x];
+    if ((unsigned)tile >= gridDim.x) tile = (int)blockIdx.x;   // a schedule not built for this grid
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
@@ -455,7 +459,8 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     int mode, int X, float* __restrict__ grad, int32_t* __restrict__ out_live,
     unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
-    const int tile = order[blockIdx.x];
+    int tile = order[blockIdx.x];
+    if ((unsigned)tile >= gridDim.x) tile = (int)blockIdx.x;   // a schedule not built for this grid
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
@@ -713,6 +718,15 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
 
 static bool saturating(int fmt) { return fmt == FB_UNORM16 || fmt == FB_UNORM8; }
 
+hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int n,
+                               const int32_t* sorted_ids, const int32_t* n_visible,
+                               const float* means2d, const float* conics, const float* opac,
+                               const float* rgb, void* ws, hipStream_t s) {
+    const RasterWs r = carve_raster_ws(ws, n, width, height, false);
+    return raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics, opac, rgb,
+                        r, s);
+}
+
 template <bool TC, bool IN>
 static void fwd_by_fmt(int rfmt, void (*&k)(int, const int32_t*, const Rec*, const uint2*,
                                              const int32_t*, const uint32_t*, int, int, int, int,
@@ -734,9 +748,11 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                              const float* rgb, void* fb, float* out_rgb, float* out_T,
                              int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s) {
     const RasterWs r = carve_raster_ws(ws, n, width, height, false);
-    hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
-                                 opac, rgb, r, s);
-    if (e0 != hipSuccess) return e0;
+    if (!(cfg.flags & GS_FLAG_REUSE_SETUP)) {
+        hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
+                                     opac, rgb, r, s);
+        if (e0 != hipSuccess) return e0;
+    }
     const int tiles_x = (width + TILE - 1) / TILE;
     const int nblocks = tiles_of(width, height);
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
@@ -768,9 +784,11 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
         hipError_t e = launch_fill_u32(r.grad, (size_t)n * GRAD_STRIDE, 0u, s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
-                                 opac, rgb, r, s);
-    if (e0 != hipSuccess) return e0;
+    if (!(cfg.flags & GS_FLAG_REUSE_SETUP)) {
+        hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
+                                     opac, rgb, r, s);
+        if (e0 != hipSuccess) return e0;
+    }
     const int tiles_x = (width + TILE - 1) / TILE;
     const int nblocks = tiles_of(width, height);
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;

@@ -198,12 +198,27 @@ def read_stats(t) -> dict:
 FB_BYTES = {"f32": 16, "f16": 8, "unorm16": 8, "bf16": 8, "unorm8": 4}
 
 
-def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, image=None, T=None,
-                   coverage=False, stats=None):
-    """gs_raster_fwd: returns dict(fb, image [3,H,W], T [H,W], coverage [H,W] or None)."""
+def raster_setup(p: Projected, cfg: RasterConfig, ws: Workspace):
+    """gs_raster_setup: builds the records, bitmap and tile schedule that a following
+    raster_forward / raster_backward with reuse_setup=True on the same workspace share. The
+    workspace is sized for the backward here, so those calls never regrow (and lose) it."""
     dev = p.means2d.device
     W, H, n = p.width, p.height, p.n
     cc, cm = cfg.c(), image_camera(W, H)
+    b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc))
+    L.gs_raster_setup(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, b, nb,
+                      _stream(dev))
+
+
+def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, image=None, T=None,
+                   coverage=False, stats=None, reuse_setup=False):
+    """gs_raster_fwd: returns dict(fb, image [3,H,W], T [H,W], coverage [H,W] or None).
+    reuse_setup: the workspace holds raster_setup's output for exactly these inputs."""
+    dev = p.means2d.device
+    W, H, n = p.width, p.height, p.n
+    cc, cm = cfg.c(), image_camera(W, H)
+    if reuse_setup:
+        cc.flags |= 2
     if fb is None:
         fb = torch.empty(L.gs_framebuffer_size(W, H, cfg.fb_format), dtype=torch.uint8, device=dev)
     if image is None:
@@ -220,11 +235,14 @@ def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, imag
 
 
 def raster_backward(p: Projected, fb, dL_dimage, cfg: RasterConfig, ws: Workspace, live=False,
-                    stats=None, out=None):
-    """gs_raster_bwd: gradients w.r.t. (means2d, conics, opacities, rgb) by splat id."""
+                    stats=None, out=None, reuse_setup=False):
+    """gs_raster_bwd: gradients w.r.t. (means2d, conics, opacities, rgb) by splat id.
+    reuse_setup: the workspace holds raster_setup's output for exactly these inputs."""
     dev = p.means2d.device
     W, H, n = p.width, p.height, p.n
     cc, cm = cfg.c(), image_camera(W, H)
+    if reuse_setup:
+        cc.flags |= 2
     if out is None:
         out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
                    opacities=torch.empty(n, device=dev), rgb=torch.empty(n, 3, device=dev))

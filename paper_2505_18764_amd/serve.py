@@ -240,10 +240,13 @@ class GpuExecutor:
         with torch.cuda.stream(s):
             ws = R.Workspace(self.dev)
             p = R.project(*sc, cam, self.cfg, ws)
-            f = R.raster_forward(p, self.cfg, ws)
+            R.raster_setup(p, self.cfg, ws)           # shared by the forward and the backward
+            f = R.raster_forward(p, self.cfg, ws, reuse_setup=True)
             out = {"image": f["image"]}
             if req.mode == FWD_BWD:
-                g2 = R.raster_backward(p, f["fb"], self.grads[(req.width, req.height)], self.cfg, ws)
+                g2 = R.raster_backward(p, f["fb"], self.grads[(req.width, req.height)], self.cfg,
+                                       ws, reuse_setup=True)
+                out["grads2d"] = {k: v for k, v in g2.items() if v is not None}
                 out["grads"] = R.project_backward(*sc, cam, self.cfg, g2)
             ev = torch.cuda.Event()
             ev.record(s)

@@ -133,6 +133,33 @@ def test_determinism():
     assert rel_l2(a["grad"], b["grad"]) <= 1e-6          # atomics only reassociate FP32 sums
 
 
+def test_shared_setup_matches_per_call_setup():
+    """gs_raster_setup once + GS_FLAG_REUSE_SETUP on the forward and the backward gives what
+    each call building its own setup gives, and matches the oracle; a workspace that held another
+    view's setup before is fully rebuilt by gs_raster_setup."""
+    W, H = 200, 136
+    s = synth.splats2d(n=6000, width=W, height=H, seed=23)
+    G = synth.image_grad(W, H, 24)
+    cfg = R.RasterConfig()
+    a = _run(s, W, H, G, cfg)
+    ws = R.Workspace()
+    other = synth.splats2d(n=6000, width=W, height=H, seed=25)
+    q = R.prepare_2d(t(other.means2d), t(other.conics), t(other.opacities), t(other.rgb),
+                     t(other.depth), W, H, cfg, ws)
+    R.raster_setup(q, cfg, ws)
+    p = R.prepare_2d(t(s.means2d), t(s.conics), t(s.opacities), t(s.rgb), t(s.depth), W, H, cfg, ws)
+    R.raster_setup(p, cfg, ws)
+    f = R.raster_forward(p, cfg, ws, coverage=True, reuse_setup=True)
+    b = R.raster_backward(p, f["fb"], t(G), cfg, ws, live=True, reuse_setup=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(f["fb"].cpu().numpy(), a["fb"])
+    np.testing.assert_array_equal(f["coverage"].cpu().numpy(), a["cov"])
+    np.testing.assert_array_equal(b["live"].cpu().numpy(), a["live"])
+    assert rel_l2(grads9(b), a["grad"]) <= 1e-6
+    ref = _oracle(s, W, H, G, oracle.OracleConfig(**BAND))
+    _check(dict(a, img=f["image"].cpu().numpy(), T=f["T"].cpu().numpy(), grad=grads9(b)), ref)
+
+
 @pytest.mark.parametrize("fmt", ["f16", "unorm16", "bf16", "unorm8"])
 @pytest.mark.parametrize("rnd", ["at_rest", "per_fragment"])
 def test_formats_against_emulating_oracle(fmt, rnd):
