@@ -210,7 +210,7 @@ def main():
 
     extra = {}
     if args.variants:
-        for mode in ("naive", "quad", "wave", "hybrid", "hybrid_lane"):
+        for mode in ("naive", "quad", "wave", "hybrid", "hybrid_lane", "tile"):
             r = run_format(head_fmt, mode, steps=max(3, args.steps // 4), warmup=1)
             s = r["stats"]
             extra[f"reduce_{mode}"] = {"raster_bwd_ms": r["stages_ms"]["raster_bwd"],

@@ -68,8 +68,11 @@ enum gs_reduce_mode {
     GS_REDUCE_WAVE = 2,         /* wave sum when >= X lanes are live, else per-fragment atomics */
     GS_REDUCE_HYBRID = 3,       /* Procedure 2: wave sum when all live lanes hold one splat and
                                    >= X are live, else quad sums */
-    GS_REDUCE_HYBRID_LANE = 4   /* Procedure 2 applied once per splat per wave after each lane
+    GS_REDUCE_HYBRID_LANE = 4,  /* Procedure 2 applied once per splat per wave after each lane
                                    has summed its own pixels' fragments in registers */
+    GS_REDUCE_TILE = 5          /* HYBRID_LANE whose wave sums are added in LDS across the
+                                   workgroup's four waves; one set of global atomics per splat
+                                   and 32x32 tile */
 };
 
 enum gs_flags {

@@ -20,7 +20,7 @@ c_sz = ctypes.c_size_t
 
 FB_FORMATS = {"f32": 0, "f16": 1, "unorm16": 2, "bf16": 3, "unorm8": 4}
 FB_ROUND = {"at_rest": 0, "per_fragment": 1}
-REDUCE_MODES = {"naive": 0, "quad": 1, "wave": 2, "hybrid": 3, "hybrid_lane": 4}
+REDUCE_MODES = {"naive": 0, "quad": 1, "wave": 2, "hybrid": 3, "hybrid_lane": 4, "tile": 5}
 OPS = {"preprocess": 0, "sort": 1, "raster_fwd": 2, "raster_bwd": 3, "preprocess_bwd": 4,
        "prepare_2d": 5, "all": 6}
 STATUS = {0: "GS_OK", 1: "GS_ERR_INVALID_ARGUMENT", 2: "GS_ERR_CAPACITY", 3: "GS_ERR_UNSUPPORTED",

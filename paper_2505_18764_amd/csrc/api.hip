@@ -81,7 +81,7 @@ int check_cfg(const gs_config* c) {
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown fb_format %d", c->fb_format);
     if (c->fb_round != GS_ROUND_AT_REST && c->fb_round != GS_ROUND_PER_FRAGMENT)
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown fb_round %d", c->fb_round);
-    if (c->reduce_mode < GS_REDUCE_NAIVE || c->reduce_mode > GS_REDUCE_HYBRID_LANE)
+    if (c->reduce_mode < GS_REDUCE_NAIVE || c->reduce_mode > GS_REDUCE_TILE)
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown reduce_mode %d", c->reduce_mode);
     if (c->reduce_threshold < 0 || c->reduce_threshold > 64)
         return fail(GS_ERR_INVALID_ARGUMENT, "reduce_threshold %d outside 0..64", c->reduce_threshold);

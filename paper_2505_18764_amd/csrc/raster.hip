@@ -26,8 +26,8 @@ constexpr int CHUNK = 4 * SPAN;    // sorted splats the workgroup tests per fill
 constexpr int BATCH = 256;         // splat records staged in LDS at once
 
 // A staged splat: a = (mean x, mean y, a', k); b = (d', opacity, r, g);
-// c = (bits of colour b, sorted position, x0 | x1 << 16, y0 | y1 << 16) with the pixel bounding
-// box [x0, x1) x [y0, y1) of the alpha >= alpha_min ellipse, clamped to the image.
+// c = (bits of colour b, sorted position, bits of p_min, 0) where p_min = log2(alpha_min / o) is
+// the least exponent whose alpha passes alpha_min.
 //
 // The conic Q = [[a, b], [b, c]] is stored in its LDL^T factors: q = d^T Q d =
 // a (dx + k dy)^2 + (det Q / a) dy^2 with k = b / a, a sum of two non-negative terms. The
@@ -152,8 +152,8 @@ __global__ __launch_bounds__(256) void k_raster_setup(
                         const double l2e = 1.4426950408889634;
                         r.a = make_float4(mx, my, -0.5f * LOG2E * a, (float)(bd / ad));
                         r.b = make_float4((float)(-0.5 * l2e * det / ad), o, cr, cg);
-                        r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, x0 | (x1 << 16),
-                                         y0 | (y1 << 16));
+                        const float pmin = (float)(log2((double)amin) - log2((double)o));
+                        r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, __float_as_uint(pmin), 0u);
                         rec[p] = r;
                         const uint32_t tx0 = x0 / TILE, tx1 = (x1 - 1) / TILE;
                         const uint32_t ty0 = y0 / TILE, ty1 = (y1 - 1) / TILE;
@@ -186,10 +186,51 @@ __global__ __launch_bounds__(256) void k_raster_setup(
 // ---- the shared walk: scan 4096 sorted splats, compact hits in order, stage records ----------
 struct Walk {
     uint16_t seg[4][SPAN];
+    uint16_t list[4][BATCH];
     int segn[4];
     int alive[4];
     Rec rec[BATCH];
 };
+
+// Per-wave culling of a staged batch. Lane j takes staged splat k0 + j and bounds its exponent
+// over each of the wave's four 8x8 sub-blocks: with c the sub-block centre and g the gradient of
+// p there, p(c + d) = p(c) + g.d + d^T Q' d <= p(c) + 3.5 (|g_x| + |g_y|) over the pixel centres
+// (|d_x|, |d_y| <= 3.5), since Q' (the pre-scaled conic, negative definite) adds nothing positive.
+// A sub-block whose bound stays below p_min (with a margin far above the FP32 error of the
+// bound) holds no fragment with alpha >= alpha_min. The splats that reach at least one
+// sub-block are compacted in order into w.list[wave] as k | mask << 8; returns their count.
+__device__ __forceinline__ int cull_batch(Walk& w, int m, int wave, int lane, uint64_t lt,
+                                          float cx0, float cy0) {
+    int cnt = 0;
+    for (int k0 = 0; k0 < m; k0 += 64) {
+        const int k = k0 + lane;
+        uint32_t mask = 0u;
+        if (k < m) {
+            const float4 A = w.rec[k].a;
+            const float4 B = w.rec[k].b;
+            const float pmin = __uint_as_float(w.rec[k].c.z);
+            const float dx0 = cx0 - A.x, dy0 = cy0 - A.y;
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb) {
+                const float dx = dx0 + (float)((sb & 1) * 8), dy = dy0 + (float)((sb >> 1) * 8);
+                const float u = fmaf(A.w, dy, dx);
+                const float au = A.z * u, dd = B.x * dy;
+                const float p0 = fmaf(au, u, dd * dy);
+                const float slack = 7.0f * (fabsf(au) + fabsf(fmaf(A.w, au, dd)));
+                const float margin = 1e-3f + 1e-5f * (slack - p0);
+                if (p0 + slack >= pmin - margin) mask |= 1u << sb;
+            }
+        }
+        const uint64_t hit = ballot(mask != 0u);
+        if (mask) w.list[wave][cnt + popc(hit & lt)] = (uint16_t)(k | (mask << 8));
+        cnt += popc(hit);
+    }
+    // the list is written and read by this wave only: order its LDS traffic
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return cnt;
+}
 
 // Tests the wave's 1024 splats of this fill against the tile, one 64-splat chunk per set bit of
 // `chunks` (16 bits, from the occupancy bitmap); writes the in-order offsets of the hits to
@@ -268,6 +309,7 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     const int qd = lane >> 2;
     const int lx = ((qd & 3) << 1) | (lane & 1), ly = ((qd >> 2) << 1) | ((lane >> 1) & 1);
     const uint64_t lt = mask_lt(lane);
+    const float cx0 = (float)wx0 + 4.f, cy0 = (float)wy0 + 4.f;   // centre of sub-block 0
 
     // C accumulates Eq. 2; with the state kept on chip, each staged batch's contributions are
     // first summed in Cb and folded into C at the batch end, so deep pixels (thousands of
@@ -307,18 +349,16 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
             __syncthreads();
             const int m = min(BATCH, total - b0);
             if (!TCULL || alive) {
-                for (int k = 0; k < m; ++k) {
+                const int nlist = cull_batch(w, m, wave, lane, lt, cx0, cy0);
+                for (int i = 0; i < nlist; ++i) {
+                    const uint32_t ent = uniform((uint32_t)w.list[wave][i]);
+                    const int k = (int)(ent & 0xFFu);
                     const float4 A = w.rec[k].a;
                     const float4 B = w.rec[k].b;
-                    const uint4 Cw = w.rec[k].c;
-                    const uint32_t bx = uniform(Cw.z), by = uniform(Cw.w);
-                    const int x0 = bx & 0xFFFF, x1 = bx >> 16, y0 = by & 0xFFFF, y1 = by >> 16;
-                    const float cb = __uint_as_float(Cw.x);
+                    const float cb = __uint_as_float(w.rec[k].c.x);
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        const int sx = wx0 + (s & 1) * 8, sy = wy0 + (s >> 1) * 8;
-                        if (x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy &&
-                            (!TCULL || ((alive >> s) & 1u))) {
+                        if (((ent >> (8 + s)) & 1u) && (!TCULL || ((alive >> s) & 1u))) {
                             const float dx = px[s] - A.x, dy = py[s] - A.y;
                             const float u = fmaf(A.w, dy, dx);
                             const float pw = fmaf(A.z * u, u, B.x * dy * dy);
@@ -336,7 +376,7 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
                                     Cb[s][1] = fmaf(wt, B.w, Cb[s][1]);
                                     Cb[s][2] = fmaf(wt, cb, Cb[s][2]);
                                 }
-                                T[s] = T[s] * (1.f - al);
+                                T[s] = T[s] - wt;                // T (1 - alpha), Eq. 5
                                 if constexpr (RFMT >= 0) {
                                     C[s][0] = fb_round<RFMT>(C[s][0]);
                                     C[s][1] = fb_round<RFMT>(C[s][1]);
@@ -404,9 +444,11 @@ struct BwdCounts {
 
 // Procedure 2 (ReduceGradient) for one splat and one wave: `g` holds this lane's gradient
 // contribution (zero when not live); `gp` is the splat's slot in the accumulation buffer.
-template <bool INSTR>
+template <bool INSTR, bool TO_LDS = false>
 __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* __restrict__ gp,
                                               int mode, int X, int lane, BwdCounts& cnt) {
+    // TO_LDS: gp points into the workgroup's LDS accumulator (the atomics there are ds_add_f32
+    // and the global commit is counted when the accumulator is flushed)
     const uint64_t m = ballot(live);
     if (m == 0) return;
     const int nl = popc(m);
@@ -425,8 +467,11 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
         for (int j = 0; j < 9; ++j) tot[j] = wave_sum(g[j]);
         if (lane == __builtin_ctzll(m))          // subgroupBallotFindLSB(reduceMask)
 #pragma unroll
-            for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, tot[j]);
-        if (INSTR && lane == 0) { cnt.sets += 1; cnt.wave_red += 1; cnt.cohesive += 1; }
+            for (int j = 0; j < 9; ++j) {
+                if constexpr (TO_LDS) atomicAdd(gp + j, tot[j]);
+                else atomic_add_f32(gp + j, tot[j]);
+            }
+        if (INSTR && lane == 0) { cnt.sets += TO_LDS ? 0 : 1; cnt.wave_red += 1; cnt.cohesive += 1; }
         return;
     }
     if (mode == GS_REDUCE_WAVE) {                // standalone subgroup reduction: no quad path
@@ -442,11 +487,36 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
     const bool leader = qm != 0u && (uint32_t)(lane & 3) == (uint32_t)__builtin_ctz(qm | 0x10u);
     if (leader)
 #pragma unroll
-        for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, g[j]);
+        for (int j = 0; j < 9; ++j) {
+            if constexpr (TO_LDS) atomicAdd(gp + j, g[j]);
+            else atomic_add_f32(gp + j, g[j]);
+        }
     if (INSTR) {
         const uint64_t lm = ballot(leader);
-        if (lane == 0) { cnt.sets += popc(lm); cnt.quad_red += 1; cnt.cohesive += 1; }
+        if (lane == 0) { cnt.sets += TO_LDS ? 0 : popc(lm); cnt.quad_red += 1; cnt.cohesive += 1; }
     }
+}
+
+// GS_REDUCE_TILE: thread t owns entry t of the staged batch's LDS accumulator; it adds the
+// entry to the splat's gradient slot (one set of global atomics per splat and tile) and clears it.
+// Called before entry t is restaged and once after the walk.
+template <bool INSTR>
+__device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Walk& w, int pend,
+                                                int tid, float* __restrict__ grad, BwdCounts& cnt) {
+    if (tid < pend) {
+        float v[9];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) { v[j] = tg[tid * 9 + j]; any = any || v[j] != 0.f; }
+        if (any) {
+            float* gp = grad + (size_t)w.rec[tid].c.y * GRAD_STRIDE;
+#pragma unroll
+            for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, v[j]);
+            if (INSTR) cnt.sets += 1;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) tg[tid * 9 + j] = 0.f;
 }
 
 template <int RFMT, bool INSTR>
@@ -459,6 +529,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     int mode, int X, float* __restrict__ grad, int32_t* __restrict__ out_live,
     unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
+    __shared__ float tg[BATCH * 9];     // GS_REDUCE_TILE: per staged splat, the tile's gradient
     int tile = order[blockIdx.x];
     if ((unsigned)tile >= gridDim.x) tile = (int)blockIdx.x;   // a schedule not built for this grid
     const int tid = threadIdx.x, lane = tid & 63;
@@ -468,7 +539,13 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     const int qd = lane >> 2;
     const int lx = ((qd & 3) << 1) | (lane & 1), ly = ((qd >> 2) << 1) | ((lane >> 1) & 1);
     const uint64_t lt = mask_lt(lane);
+    const float cx0 = (float)wx0 + 4.f, cy0 = (float)wy0 + 4.f;   // centre of sub-block 0
     const size_t P = (size_t)W * H;
+    const bool tile_acc = (mode == GS_REDUCE_TILE);
+    int pend = 0;                       // staged entries whose LDS gradients are not yet flushed
+    if (tile_acc)
+#pragma unroll
+        for (int j = 0; j < 9; ++j) tg[tid * 9 + j] = 0.f;
 
     // Procedure 1's per-pixel state (C', T), initialised to (C, 1) from the framebuffer, and the
     // read-only dL/dC.
@@ -498,7 +575,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     BwdCounts cnt = {0, 0, 0, 0, 0, 0};
     uint32_t nq = 0;
-    const bool lane_acc = (mode == GS_REDUCE_HYBRID_LANE);
+    const bool lane_acc = (mode == GS_REDUCE_HYBRID_LANE || mode == GS_REDUCE_TILE);
 
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
     for (int base = 0; base < nvis; base += CHUNK) {
@@ -511,15 +588,18 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
         if (INSTR) nq += total;
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
+            if (tile_acc) { flush_tile_grad<INSTR>(tg, w, pend, tid, grad, cnt); pend = 0; }
             stage(w, rec, base, b0, total, tid);
             __syncthreads();
             const int m = min(BATCH, total - b0);
-            for (int k = 0; k < m && alive; ++k) {
+            pend = m;
+            const int nlist = alive ? cull_batch(w, m, wave, lane, lt, cx0, cy0) : 0;
+            for (int i = 0; i < nlist && alive; ++i) {
+                const uint32_t ent = uniform((uint32_t)w.list[wave][i]);
+                const int k = (int)(ent & 0xFFu);
                 const float4 A = w.rec[k].a;
                 const float4 B = w.rec[k].b;
                 const uint4 Cw = w.rec[k].c;
-                const uint32_t bx = uniform(Cw.z), by = uniform(Cw.w);
-                const int x0 = bx & 0xFFFF, x1 = bx >> 16, y0 = by & 0xFFFF, y1 = by >> 16;
                 const float cr = B.z, cg = B.w, cb = __uint_as_float(Cw.x);
                 float* gp = grad + (size_t)uniform(Cw.y) * GRAD_STRIDE;
                 float acc[9];
@@ -528,9 +608,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                 bool acc_live = false;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const int sx = wx0 + (s & 1) * 8, sy = wy0 + (s >> 1) * 8;
-                    if (!(x0 < sx + 8 && x1 > sx && y0 < sy + 8 && y1 > sy && ((alive >> s) & 1u)))
-                        continue;
+                    if (!((ent >> (8 + s)) & 1u) || !((alive >> s) & 1u)) continue;
                     const float dx = px[s] - A.x, dy = py[s] - A.y;
                     const float u = fmaf(A.w, dy, dx);
                     const float au = A.z * u;
@@ -558,7 +636,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                         Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
                         Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
                         Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
-                        T[s] = Ti * (1.f - al);
+                        T[s] = Ti - wt;                                   // Eq. 5
                         if constexpr (RFMT >= 0) {
                             Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
                             Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
@@ -593,7 +671,8 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                     }
                     if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
                 }
-                if (lane_acc) reduce_commit<INSTR>(acc, acc_live, gp, GS_REDUCE_HYBRID, X, lane, cnt);
+                if (tile_acc) reduce_commit<INSTR, true>(acc, acc_live, tg + k * 9, GS_REDUCE_HYBRID, X, lane, cnt);
+                else if (lane_acc) reduce_commit<INSTR>(acc, acc_live, gp, GS_REDUCE_HYBRID, X, lane, cnt);
             }
             if (lane == 0) w.alive[wave] = (int)alive;
             __syncthreads();
@@ -601,6 +680,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
         }
         if (stop) break;
     }
+    if (tile_acc) flush_tile_grad<INSTR>(tg, w, pend, tid, grad, cnt);
 
     if (INSTR && out_live) {
 #pragma unroll
@@ -612,11 +692,12 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     }
     if (INSTR && stats) {
         const uint32_t e = wave_sum_u32(cnt.evaluated), l = wave_sum_u32(cnt.live);
+        const uint32_t sets = wave_sum_u32(cnt.sets);   // flushes count on every lane
         if (lane == 0) {
             if (wave == 0) atomicAdd(&stats[3], (unsigned long long)nq);
             atomicAdd(&stats[4], (unsigned long long)e);
             atomicAdd(&stats[5], (unsigned long long)l);
-            atomicAdd(&stats[6], (unsigned long long)cnt.sets);
+            atomicAdd(&stats[6], (unsigned long long)sets);
             atomicAdd(&stats[7], (unsigned long long)cnt.wave_red);
             atomicAdd(&stats[8], (unsigned long long)cnt.quad_red);
             atomicAdd(&stats[9], (unsigned long long)cnt.cohesive);

@@ -101,7 +101,7 @@ def _oracle_projected(sc, cam):
     return pre, order, ids, arr
 
 
-@pytest.mark.parametrize("fmt,mode", [("f32", "hybrid"), ("f32", "hybrid_lane"), ("f32", "naive")])
+@pytest.mark.parametrize("fmt,mode", [("f32", "hybrid"), ("f32", "hybrid_lane"), ("f32", "tile"), ("f32", "naive")])
 def test_raster_on_projected_scene(fmt, mode):
     """The raster stage alone on a dense clustered scene (depth complexity in the hundreds)."""
     sc, cam = _scene(60_000, 7, 256, 192)

@@ -66,7 +66,7 @@ def _check(out, ref, img_tol=1e-5, grad_tol=1e-4, counts=True):
     return e
 
 
-@pytest.mark.parametrize("mode", ["naive", "quad", "wave", "hybrid", "hybrid_lane"])
+@pytest.mark.parametrize("mode", ["naive", "quad", "wave", "hybrid", "hybrid_lane", "tile"])
 def test_cfg1_parity_all_reduce_modes(mode):
     c = synth.CFG1
     W, H = c["width"], c["height"]
