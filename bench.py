@@ -22,9 +22,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FLOPs per fragment of the method's own arithmetic (see DESIGN.md):
+# Algorithmic FLOPs per fragment of the method's own arithmetic:
 FLOP_FWD_PER_COVERED = 24   # alpha of one fragment + the blend of Eq. 2
-FLOP_BWD_PER_LIVE = 72      # alpha, Eqs. 3/5/6/7, the chain rule to 9 parameters, their reduction
+FLOP_BWD_PER_LIVE = 69      # alpha, Eqs. 3/5/6/7, the chain rule to 9 parameters, their reduction
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
@@ -71,8 +71,8 @@ def _traffic(kernel_key):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
-              "component (see DESIGN.md for how it would shard).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the path has no multi-GPU "
+              "component; views are independent and would shard one view per GPU.", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth

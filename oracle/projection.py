@@ -8,8 +8,11 @@ vector; t = W mu + tau; mu_2D = proj(t); Sigma_2D = J W Sigma_3D W^T J^T (+ eps2
 dilation the paper does not state; common practice); conic = Sigma_2D^{-1}; colour from real
 spherical harmonics of degree <= 3 evaluated at the view direction. The paper gives neither
 the SH basis nor its offset; the readings used here (orthonormal real SH, +0.5 offset, clamp
-at 0) are listed in the design notes. Frustum culling (Sec. 4.1) drops splats that cannot put
-a fragment with alpha >= alpha_min on a pixel centre.
+at 0) are listed in the design notes. The tests pin the basis by orthonormality and the
+addition theorem, which fix every function up to its sign: the sign convention of the m != 0
+functions (no Condon-Shortley phase, Y_1,-1 ~ y, Y_1,0 ~ z, Y_1,1 ~ x) is parity unpinned.
+Frustum culling (Sec. 4.1) drops splats that cannot put a fragment with alpha >= alpha_min on a
+pixel centre.
 
 Every arithmetic step is written so that it also runs on complex128 inputs. The backward is
 then the exact derivative of this forward by the complex-step method,
