@@ -36,7 +36,7 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
     ap.add_argument("--formats", default="f16,f32")
-    ap.add_argument("--reduce", default="hybrid_lane")
+    ap.add_argument("--reduce", default="tile")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-blocks", type=int, default=96)
     ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")

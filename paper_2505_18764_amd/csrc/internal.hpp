@@ -32,11 +32,22 @@ struct RasterWs {
     void* rec;         // [n] records in sorted order
     void* rect;        // [n] uint2 tile rectangles
     float* grad;       // [n * GRAD_STRIDE] (backward only)
-    unsigned long long* counters;  // [16] stats scratch
-    uint32_t* weights; // [tiles] sampled splat count per tile
-    int32_t* order;    // [tiles] tiles by decreasing weight
+    unsigned long long* counters;  // [16] planner scratch
+    uint32_t* weights; // [tiles] splat count per tile
+    int32_t* order;    // [tiles] tiles, heaviest first
     uint32_t* bits;    // [tiles][wpr] occupancy bitmap: one bit per 64 sorted splats
     int wpr;           // words per bitmap row (0: no bitmap)
+    // depth-split forward (split != 0): per-tile splat counts of each 2048-position column,
+    // work items (tile, first column, end column, partial slot), their order, per-tile segment
+    // count and first item, and FP32 partial states of the split tiles' segments
+    int split;
+    uint16_t* colcnt;  // [tiles][wpr]
+    int4* items;       // [2 tiles]
+    uint32_t* item_w;  // [2 tiles]
+    int32_t* item_order; // [2 tiles], -1 past the item count
+    int32_t* tile_first; // [tiles]
+    int32_t* tile_k;     // [tiles]
+    float4* partial;     // [2 tiles][TILE * TILE]
 };
 size_t raster_ws_bytes(int n, int width, int height, bool bwd);
 RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd);

@@ -48,41 +48,186 @@ constexpr float LOG2E = 1.4426950408889634f;
 constexpr int WEIGHT_SAMPLE = 8;        // every 8th sorted splat votes for the tiles it touches
 constexpr int CHUNK_SPLATS = 64;        // sorted splats per bit of the tile occupancy bitmap
 constexpr size_t BITMAP_BUDGET = 256u << 20;  // the bitmap is skipped above this many bytes
-constexpr int MAX_ORDERED_TILES = 8192; // tiles ordered by weight in one workgroup (LDS sort)
 
-// Tile schedule. The work of a tile grows with the number of splats over it, which on clustered
-// scenes varies by orders of magnitude across the screen. Workgroups are dispatched in block
-// order (round-robin over the 8 XCDs, then to whichever CU has room), so listing the tiles by
-// decreasing estimated work starts the heaviest tiles first and spreads them over all XCDs:
-// a longest-processing-time-first schedule.
-__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ weights,
-                                                     int ntiles, int32_t* __restrict__ order) {
-    __shared__ unsigned long long key[MAX_ORDERED_TILES];
+// ---- schedule ------------------------------------------------------------------------------
+// The work of a tile grows with the number of splats over it, which on clustered scenes varies
+// by orders of magnitude across the screen. Workgroups are dispatched in block order (round-robin
+// over the 8 XCDs, then to whichever CU has room), so listing the work heaviest first spreads the
+// heavy tiles over all XCDs and starts them first: a longest-processing-time-first schedule. The
+// order only has to be approximate, so it is a counting sort over weight buckets.
+//
+// Depth split. All tiles of a view are resident at once, so the forward lasts as long as its
+// densest tile, whose workgroup walks its whole splat list alone. Compositing is associative:
+// (C1, T1) then (C2, T2) gives (C1 + T1 C2, T1 T2). A tile heavier than the mean weight is
+// therefore cut into up to MAX_SEGMENTS depth segments at 2048-position column boundaries, each
+// carrying about the same number of splats (from exact per-column counts); each segment is a
+// work item that composites from (0, 1) into an FP32 partial state, and k_raster_merge combines
+// the segments in depth order. Only the at-rest, non-T-culled forward splits: T-culling and
+// per-fragment rounding of the stored state need the segments' inputs in sequence.
+constexpr int NBUCKETS = 1024;
+constexpr int MAX_SEGMENTS = 8;
+constexpr int MAX_SPLIT_TILES = 4096;
+
+// out[0 .. count) = indices ordered by decreasing bucket of w (one workgroup of 1024 threads);
+// out[count .. pad) = -1.
+__device__ void bucket_order(const uint32_t* __restrict__ w, int count, uint32_t wmax,
+                             int32_t* __restrict__ out, int pad, uint32_t* s_hist) {
     const int tid = threadIdx.x;
-    if (ntiles > MAX_ORDERED_TILES) {
-        for (int i = tid; i < ntiles; i += blockDim.x) order[i] = i;
+    for (int b = tid; b < NBUCKETS; b += blockDim.x) s_hist[b] = 0u;
+    __syncthreads();
+    const unsigned long long den = (unsigned long long)wmax + 1ull;
+    for (int i = tid; i < count; i += blockDim.x) {
+        const int b = NBUCKETS - 1 - (int)((unsigned long long)w[i] * NBUCKETS / den);
+        atomicAdd(&s_hist[b], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the NBUCKETS counts (blockDim.x == NBUCKETS)
+    uint32_t v = s_hist[tid];
+    __syncthreads();
+    for (int o = 1; o < NBUCKETS; o <<= 1) {
+        const uint32_t add = tid >= o ? s_hist[tid - o] : 0u;
+        __syncthreads();
+        s_hist[tid] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = s_hist[tid];
+    __syncthreads();
+    s_hist[tid] = incl - v;
+    __syncthreads();
+    for (int i = tid; i < count; i += blockDim.x) {
+        const int b = NBUCKETS - 1 - (int)((unsigned long long)w[i] * NBUCKETS / den);
+        out[atomicAdd(&s_hist[b], 1u)] = i;      // order within a bucket is arbitrary
+    }
+    for (int i = count + tid; i < pad; i += blockDim.x) out[i] = -1;
+}
+
+// One workgroup: the tile order; with `split`, each tile's segment count k_t (its weight over
+// the mean tile weight, rounded up, at most MAX_SEGMENTS) and the first item of each tile (an
+// exclusive scan of k_t); counters[0] = number of items.
+__global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
+    const uint32_t* __restrict__ weights, int ntiles, int32_t* __restrict__ order, int split,
+    int32_t* __restrict__ tile_k, int32_t* __restrict__ tile_first,
+    unsigned long long* __restrict__ counters) {
+    __shared__ uint32_t s_hist[NBUCKETS];
+    __shared__ unsigned long long s_tot;
+    __shared__ uint32_t s_max;
+    const int tid = threadIdx.x;
+    if (tid == 0) { s_tot = 0ull; s_max = 0u; }
+    __syncthreads();
+    unsigned long long tot = 0ull;
+    uint32_t mx = 0u;
+    for (int t = tid; t < ntiles; t += blockDim.x) { tot += weights[t]; mx = max(mx, weights[t]); }
+    atomicAdd(&s_tot, tot);
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    const unsigned long long total = s_tot;
+    const uint32_t wmax = s_max;
+    bucket_order(weights, ntiles, wmax, order, ntiles, s_hist);
+    if (!split) return;
+    __syncthreads();
+    // k_t with cap = ceil(mean weight): sum of k_t <= total / cap + ntiles <= 2 ntiles
+    const unsigned long long cap = max(1ull, (total + ntiles - 1) / (unsigned long long)ntiles);
+    // exclusive scan of k_t over tiles: thread tid owns tiles [4 tid, 4 tid + 4) (ntiles <= 4096)
+    int kk[4], loc = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = 4 * tid + r;
+        int k = 0;
+        if (t < ntiles) {
+            const unsigned long long q = ((unsigned long long)weights[t] + cap - 1) / cap;
+            k = (int)min((unsigned long long)MAX_SEGMENTS, max(1ull, q));
+            tile_k[t] = k;
+        }
+        kk[r] = k;
+        loc += k;
+    }
+    s_hist[tid] = (uint32_t)loc;
+    __syncthreads();
+    for (int o = 1; o < NBUCKETS; o <<= 1) {
+        const uint32_t add = tid >= o ? s_hist[tid - o] : 0u;
+        __syncthreads();
+        s_hist[tid] += add;
+        __syncthreads();
+    }
+    int run = (int)s_hist[tid] - loc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int t = 4 * tid + r;
+        if (t < ntiles) tile_first[t] = run;
+        run += kk[r];
+    }
+    if (tid == NBUCKETS - 1) counters[0] = (unsigned long long)s_hist[tid];
+}
+
+// One wave per tile: the tile's work items. A tile with k_t = 1 is one item over all columns
+// writing the framebuffer directly (slot -1); otherwise the column counts are scanned and cut
+// where the running count first reaches j w_t / k_t.
+__global__ __launch_bounds__(64) void k_plan_cuts(
+    const uint32_t* __restrict__ weights, const uint16_t* __restrict__ colcnt, int wpr, int ntiles,
+    const int32_t* __restrict__ tile_k, const int32_t* __restrict__ tile_first,
+    int4* __restrict__ items, uint32_t* __restrict__ item_w) {
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const int k = tile_k[t], f = tile_first[t];
+    const uint32_t w = weights[t];
+    if (k < 1 || f < 0 || f + k > 2 * ntiles) return;
+    if (k == 1) {
+        if (lane == 0) { items[f] = make_int4(t, 0, wpr, -1); item_w[f] = w; }
         return;
     }
-    int m = 1;
-    while (m < ntiles) m <<= 1;
-    for (int i = tid; i < m; i += blockDim.x)
-        key[i] = i < ntiles ? ((unsigned long long)(0xFFFFFFFFu - weights[i]) << 32) | (uint32_t)i
-                            : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= m; k <<= 1) {          // bitonic sort, ascending
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < m; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const unsigned long long a = key[i], b = key[l];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) { key[i] = b; key[l] = a; }
-                }
+    int cut[MAX_SEGMENTS + 1];
+    uint32_t cum[MAX_SEGMENTS + 1];
+    cut[0] = 0; cum[0] = 0u;
+#pragma unroll
+    for (int j = 1; j <= MAX_SEGMENTS; ++j) { cut[j] = wpr; cum[j] = w; }
+    int found = 1;                                   // next cut to find
+    uint32_t base = 0u;
+    const uint16_t* row = colcnt + (size_t)t * wpr;
+    for (int c0 = 0; c0 < wpr && found < k; c0 += 64) {
+        uint32_t v = (c0 + lane < wpr) ? row[c0 + lane] : 0u;
+        for (int o = 1; o < 64; o <<= 1) {          // inclusive prefix over the wave
+            const uint32_t u = __shfl_up(v, o);
+            if (lane >= o) v += u;
+        }
+        const uint32_t incl = base + v;
+#pragma unroll
+        for (int j = 1; j < MAX_SEGMENTS; ++j) {
+            if (j >= k || j < found) continue;
+            const uint32_t target = (uint32_t)(((unsigned long long)w * j + k - 1) / k);
+            const uint64_t m = ballot(incl >= target && c0 + lane < wpr);
+            if (m) {
+                const int l = __builtin_ctzll(m);
+                cut[j] = c0 + l + 1;
+                cum[j] = __shfl(incl, l);
+                found = j + 1;
             }
-            __syncthreads();
+        }
+        base = __shfl(incl, 63);
+    }
+    if (lane == 0) {
+        cut[k] = wpr; cum[k] = w;
+        for (int j = 0; j < k; ++j) {
+            const int a = cut[j], b = max(cut[j], cut[j + 1]);
+            items[f + j] = make_int4(t, a, b, f + j);
+            item_w[f + j] = cum[j + 1] >= cum[j] ? cum[j + 1] - cum[j] : 0u;
         }
     }
-    for (int i = tid; i < ntiles; i += blockDim.x) order[i] = (int32_t)(key[i] & 0xFFFFFFFFu);
+}
+
+// One workgroup: items heaviest first; item_order padded with -1 to 2 ntiles.
+__global__ __launch_bounds__(NBUCKETS) void k_plan_items(
+    const uint32_t* __restrict__ item_w, int ntiles, const unsigned long long* __restrict__ counters,
+    int32_t* __restrict__ item_order) {
+    __shared__ uint32_t s_hist[NBUCKETS];
+    __shared__ uint32_t s_max;
+    const int cap = 2 * ntiles;
+    const int count = (int)min((unsigned long long)cap, counters[0]);
+    if (threadIdx.x == 0) s_max = 0u;
+    __syncthreads();
+    uint32_t mx = 0u;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) mx = max(mx, item_w[i]);
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    bucket_order(item_w, count, s_max, item_order, cap, s_hist);
 }
 
 __device__ __forceinline__ bool rect_hit(uint2 r, uint32_t tx, uint32_t ty) {
@@ -107,7 +252,8 @@ __global__ __launch_bounds__(256) void k_raster_setup(
     const float* __restrict__ means2d, const float* __restrict__ conics,
     const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
     int saturate, int tiles_x, int ntiles, Rec* __restrict__ rec, uint2* __restrict__ rect,
-    uint32_t* __restrict__ weights, uint32_t* __restrict__ bits, int wpr) {
+    uint32_t* __restrict__ weights, uint32_t* __restrict__ bits, int wpr,
+    uint16_t* __restrict__ colcnt) {
     __shared__ uint32_t s_bits[MAX_LDS_TILES];
     __shared__ uint32_t s_cnt[MAX_LDS_TILES];
     const bool in_lds = ntiles <= MAX_LDS_TILES;
@@ -179,6 +325,7 @@ __global__ __launch_bounds__(256) void k_raster_setup(
     if (in_lds)
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
             if (wpr > 0) bits[(size_t)t * wpr + blockIdx.x] = s_bits[t];
+            if (colcnt) colcnt[(size_t)t * wpr + blockIdx.x] = (uint16_t)s_cnt[t];   // <= 2048
             if (s_cnt[t]) atomicAdd(&weights[t], s_cnt[t]);
         }
 }
@@ -291,17 +438,31 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
 }
 
 // ---- forward -------------------------------------------------------------------------------
+// One workgroup per work item: a whole tile (items == nullptr: block b takes tile order[b]) or,
+// in the depth-split forward, one depth segment of a tile (columns [c_begin, c_end) of 2048
+// sorted positions), which writes its FP32 (C, T) to partial[slot] instead of the framebuffer.
 template <int RFMT, bool TCULL, bool INSTR>
 __global__ __launch_bounds__(NT) void k_raster_fwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
     const uint2* __restrict__ rect, const int32_t* __restrict__ order,
-    const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x,
+    const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x, int ntiles,
+    const int4* __restrict__ items, const int32_t* __restrict__ item_order,
+    float4* __restrict__ partial,
     float amin, float amax, float tmin, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
     float* __restrict__ out_T, int32_t* __restrict__ out_cov,
     unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
-    int tile = order[blockIdx.x];
-    if ((unsigned)tile >= gridDim.x) tile = (int)blockIdx.x;   // a schedule not built for this grid
+    int tile, c_begin = 0, c_end = wpr, slot = -1;
+    if (items) {
+        const int it = item_order[blockIdx.x];
+        if (it < 0 || it >= 2 * ntiles) return;               // past the item count
+        const int4 v = items[it];
+        tile = v.x; c_begin = v.y; c_end = v.z; slot = v.w;
+        if ((unsigned)tile >= (unsigned)ntiles || slot >= 2 * ntiles) return;
+    } else {
+        tile = order[blockIdx.x];
+        if ((unsigned)tile >= (unsigned)ntiles) tile = (int)blockIdx.x;   // a schedule not built for this grid
+    }
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
@@ -333,10 +494,15 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     int nvis = *nvis_ptr;
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     uint32_t nq = 0;
+    // sorted positions [p0, p1) of this item; segment bounds are multiples of SETUP_SPAN
+    const int p0 = c_begin * SETUP_SPAN;
+    const int p1 = c_end >= wpr ? nvis : min(nvis, c_end * SETUP_SPAN);
 
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
-    for (int base = 0; base < nvis; base += CHUNK) {
-        const uint64_t wbits = window_bits(trow, wpr, base);
+    for (int base = (p0 / CHUNK) * CHUNK; base < p1; base += CHUNK) {
+        uint64_t wbits = window_bits(trow, wpr, base);
+        if (base < p0) wbits &= ~0xFFFFFFFFull;                  // first half before the segment
+        if (p1 <= base + SETUP_SPAN) wbits &= 0xFFFFFFFFull;      // second half after it
         if (wbits == 0) continue;                 // no splat of this fill touches the tile
         scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt,
                   (uint32_t)(wbits >> (16 * wave)) & 0xFFFFu);
@@ -407,6 +573,15 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
         if (TCULL && stop) break;
     }
 
+    if (slot >= 0) {                              // a depth segment: FP32 partial state
+        float4* part = partial + (size_t)slot * (TILE * TILE);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int lxp = (wave & 1) * 16 + (s & 1) * 8 + lx, lyp = (wave >> 1) * 16 + (s >> 1) * 8 + ly;
+            part[lyp * TILE + lxp] = make_float4(C[s][0], C[s][1], C[s][2], T[s]);
+        }
+        return;
+    }
     const size_t P = (size_t)W * H;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -433,6 +608,36 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
             atomicAdd(&stats[1], (unsigned long long)e);
             atomicAdd(&stats[2], (unsigned long long)c);
         }
+    }
+}
+
+// Depth-split forward: combines a split tile's segment states in depth order,
+// (C, T) <- (C + T C_j, T T_j), and writes the framebuffer and the FP32 copies.
+__global__ __launch_bounds__(256) void k_raster_merge(
+    int ntiles, int tiles_x, int W, int H, const int32_t* __restrict__ tile_k,
+    const int32_t* __restrict__ tile_first, const float4* __restrict__ partial, int fb_fmt,
+    void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T) {
+    const int t = blockIdx.x;
+    const int k = tile_k[t], f = tile_first[t];
+    if (k <= 1 || f < 0 || f + k > 2 * ntiles) return;
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    const size_t P = (size_t)W * H;
+    for (int lp = threadIdx.x; lp < TILE * TILE; lp += blockDim.x) {
+        const int X = tx * TILE + (lp % TILE), Y = ty * TILE + (lp / TILE);
+        if (X >= W || Y >= H) continue;
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+        for (int j = 0; j < k; ++j) {
+            const float4 v = partial[(size_t)(f + j) * (TILE * TILE) + lp];
+            C0 = fmaf(T, v.x, C0);
+            C1 = fmaf(T, v.y, C1);
+            C2 = fmaf(T, v.z, C2);
+            T *= v.w;
+        }
+        const size_t i = (size_t)Y * W + X;
+        float4 v = make_float4(C0, C1, C2, T);
+        fb_store(fb, fb_fmt, i, v);                 // v becomes the stored (rounded) state
+        if (out_rgb) { out_rgb[i] = v.x; out_rgb[P + i] = v.y; out_rgb[2 * P + i] = v.z; }
+        if (out_T) out_T[i] = v.w;
     }
 }
 
@@ -754,10 +959,18 @@ static int bitmap_wpr(int n, int width, int height) {
     return (n > 0 && nt <= (size_t)MAX_LDS_TILES && nt * wpr * 4 <= BITMAP_BUDGET) ? (int)wpr : 0;
 }
 
+static bool split_ok(int n, int width, int height) {
+    return bitmap_wpr(n, width, height) > 0 && tiles_of(width, height) <= MAX_SPLIT_TILES;
+}
+
 size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
     const size_t nt = (size_t)tiles_of(width, height);
+    const size_t wpr = (size_t)bitmap_wpr(n, width, height);
     size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up(16 * 8) +
-               align_up(nt * 4) * 2 + align_up(nt * (size_t)bitmap_wpr(n, width, height) * 4);
+               align_up(nt * 4) * 2 + align_up(nt * wpr * 4);
+    if (split_ok(n, width, height))
+        b += align_up(nt * wpr * 2) + align_up(2 * nt * 16) + 2 * align_up(2 * nt * 4) +
+             2 * align_up(nt * 4) + align_up(2 * nt * TILE * TILE * 16);
     if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4);
     return b;
 }
@@ -773,11 +986,24 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     r.order = (int32_t*)p;    p += align_up(nt * 4);
     r.wpr = bitmap_wpr(n, width, height);
     r.bits = (uint32_t*)p;    p += align_up(nt * (size_t)r.wpr * 4);
+    r.split = split_ok(n, width, height) ? 1 : 0;
+    r.colcnt = nullptr; r.items = nullptr; r.item_w = nullptr; r.item_order = nullptr;
+    r.tile_first = nullptr; r.tile_k = nullptr; r.partial = nullptr;
+    if (r.split) {
+        r.colcnt = (uint16_t*)p;    p += align_up(nt * (size_t)r.wpr * 2);
+        r.items = (int4*)p;         p += align_up(2 * nt * 16);
+        r.item_w = (uint32_t*)p;    p += align_up(2 * nt * 4);
+        r.item_order = (int32_t*)p; p += align_up(2 * nt * 4);
+        r.tile_first = (int32_t*)p; p += align_up(nt * 4);
+        r.tile_k = (int32_t*)p;     p += align_up(nt * 4);
+        r.partial = (float4*)p;     p += align_up(2 * nt * TILE * TILE * 16);
+    }
     r.grad = bwd ? (float*)p : nullptr;
     return r;
 }
 
-// Records, tile rectangles, tile weights and the tile schedule.
+// Records, tile rectangles, tile weights, the occupancy bitmap and the schedule (tile order and,
+// where the workspace allows it, the depth-split work items).
 static hipError_t raster_setup(const gs_config& cfg, int width, int height, int n,
                                const int32_t* sorted_ids, const int32_t* n_visible,
                                const float* means2d, const float* conics, const float* opac,
@@ -791,9 +1017,17 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
         hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN), dim3(256), 0, s,
                            n, sorted_ids, n_visible, means2d, conics, opac, rgb, width, height,
                            cfg.alpha_min, sat, tiles_x, ntiles, (Rec*)r.rec, (uint2*)r.rect,
-                           r.weights, r.bits, r.wpr);
+                           r.weights, r.bits, r.wpr, r.colcnt);
     }
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, r.weights, ntiles, r.order);
+    hipLaunchKernelGGL(k_plan_tiles, dim3(1), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
+                       r.split, r.tile_k, r.tile_first, r.counters);
+    if (r.split) {
+        hipLaunchKernelGGL(k_plan_cuts, dim3(ntiles), dim3(64), 0, s, r.weights,
+                           (const uint16_t*)r.colcnt, r.wpr, ntiles, (const int32_t*)r.tile_k,
+                           (const int32_t*)r.tile_first, r.items, r.item_w);
+        hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(NBUCKETS), 0, s, (const uint32_t*)r.item_w,
+                           ntiles, (const unsigned long long*)r.counters, r.item_order);
+    }
     return hipGetLastError();
 }
 
@@ -808,18 +1042,20 @@ hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int 
                         r, s);
 }
 
+using FwdKernel = void (*)(int, const int32_t*, const Rec*, const uint2*, const int32_t*,
+                          const uint32_t*, int, int, int, int, int, const int4*, const int32_t*,
+                          float4*, float, float, float, int, void*, float*, float*, int32_t*,
+                          unsigned long long*);
+
 template <bool TC, bool IN>
-static void fwd_by_fmt(int rfmt, void (*&k)(int, const int32_t*, const Rec*, const uint2*,
-                                             const int32_t*, const uint32_t*, int, int, int, int,
-                                             float, float, float, int, void*, float*, float*,
-                                             int32_t*, unsigned long long*)) {
+static FwdKernel fwd_by_fmt(int rfmt) {
     switch (rfmt) {
-    case FB_F32: k = k_raster_fwd<FB_F32, TC, IN>; break;
-    case FB_F16: k = k_raster_fwd<FB_F16, TC, IN>; break;
-    case FB_UNORM16: k = k_raster_fwd<FB_UNORM16, TC, IN>; break;
-    case FB_BF16: k = k_raster_fwd<FB_BF16, TC, IN>; break;
-    case FB_UNORM8: k = k_raster_fwd<FB_UNORM8, TC, IN>; break;
-    default: k = k_raster_fwd<-1, TC, IN>; break;
+    case FB_F32: return k_raster_fwd<FB_F32, TC, IN>;
+    case FB_F16: return k_raster_fwd<FB_F16, TC, IN>;
+    case FB_UNORM16: return k_raster_fwd<FB_UNORM16, TC, IN>;
+    case FB_BF16: return k_raster_fwd<FB_BF16, TC, IN>;
+    case FB_UNORM8: return k_raster_fwd<FB_UNORM8, TC, IN>;
+    default: return k_raster_fwd<-1, TC, IN>;
     }
 }
 
@@ -835,21 +1071,27 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
         if (e0 != hipSuccess) return e0;
     }
     const int tiles_x = (width + TILE - 1) / TILE;
-    const int nblocks = tiles_of(width, height);
+    const int ntiles = tiles_of(width, height);
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool tcull = cfg.t_min_fwd > 0.f;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_cov;
-    void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
-              int, int, int, float, float, float, int, void*, float*, float*, int32_t*,
-              unsigned long long*) = nullptr;
-    if (tcull) { if (instr) fwd_by_fmt<true, true>(rfmt, k); else fwd_by_fmt<true, false>(rfmt, k); }
-    else { if (instr) fwd_by_fmt<false, true>(rfmt, k); else fwd_by_fmt<false, false>(rfmt, k); }
-    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
-                       (const uint2*)r.rect, (const int32_t*)r.order, (const uint32_t*)r.bits,
-                       r.wpr, width, height, tiles_x,
+    // the depth split needs the at-rest state, no T-culling and no per-pixel counters
+    const bool split = r.split && rfmt < 0 && !tcull && !instr;
+    FwdKernel k = tcull ? (instr ? fwd_by_fmt<true, true>(rfmt) : fwd_by_fmt<true, false>(rfmt))
+                        : (instr ? fwd_by_fmt<false, true>(rfmt) : fwd_by_fmt<false, false>(rfmt));
+    hipLaunchKernelGGL(k, dim3(split ? 2 * ntiles : ntiles), dim3(NT), 0, s, n, n_visible,
+                       (const Rec*)r.rec, (const uint2*)r.rect, (const int32_t*)r.order,
+                       (const uint32_t*)r.bits, r.wpr, width, height, tiles_x, ntiles,
+                       split ? (const int4*)r.items : nullptr,
+                       split ? (const int32_t*)r.item_order : nullptr, split ? r.partial : nullptr,
                        cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.fb_format, fb, out_rgb, out_T,
                        out_cov,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !split) return e;
+    hipLaunchKernelGGL(k_raster_merge, dim3(ntiles), dim3(256), 0, s, ntiles, tiles_x, width, height,
+                       (const int32_t*)r.tile_k, (const int32_t*)r.tile_first,
+                       (const float4*)r.partial, cfg.fb_format, fb, out_rgb, out_T);
     return hipGetLastError();
 }
 

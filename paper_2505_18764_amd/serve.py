@@ -206,7 +206,7 @@ class GpuExecutor:
         self.dev = torch.device(device)
         self.scenes = scenes                      # id -> (means3d, scales, quats, opac, sh)
         self.cameras = cameras                    # (W, H) -> camera object
-        self.cfg = cfg or RasterConfig(fb_format="f16", reduce_mode="hybrid_lane")
+        self.cfg = cfg or RasterConfig(fb_format="f16", reduce_mode="tile")
         self.streams = {}
         self.grads = {}
         g = np.random.default_rng(grad_seed)

@@ -82,7 +82,7 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     hidden = synth.scene3d(args.n, seed=c["seed_hidden"])
     train0 = synth.scene3d(args.n, seed=c["seed_train"])
-    cfg = RasterConfig(fb_format=args.fb_format, reduce_mode="hybrid_lane")
+    cfg = RasterConfig(fb_format=args.fb_format, reduce_mode="tile")
     ws = Workspace(dev)
     with torch.no_grad():
         targets = [rasterize_gaussians(t(hidden.means3d), t(hidden.scales), t(hidden.quats),

@@ -133,6 +133,41 @@ def test_determinism():
     assert rel_l2(a["grad"], b["grad"]) <= 1e-6          # atomics only reassociate FP32 sums
 
 
+def test_depth_split_forward():
+    """The forward without counters (the configuration the benchmark times) splits tiles heavier
+    than the mean into depth segments and merges them; a dense centre guarantees splits. Image
+    and T against the oracle, and against the unsplit (instrumented) forward; gradients from the
+    split forward's framebuffer against the oracle."""
+    W, H = 256, 192
+    g = np.random.default_rng(27)
+    a = synth.splats2d(n=3000, width=W, height=H, seed=27)
+    b = synth.splats2d(n=20000, width=48, height=40, seed=28)      # a dense 48x40 patch ...
+    b.means2d[:] += np.array([104.0, 76.0], np.float32)             # ... moved to the centre
+    s = synth.Splats2D(means2d=np.concatenate([a.means2d, b.means2d]),
+                       conics=np.concatenate([a.conics, b.conics]),
+                       opacities=np.concatenate([a.opacities, b.opacities]),
+                       rgb=np.concatenate([a.rgb, b.rgb]),
+                       depth=g.permutation(np.concatenate([a.depth, b.depth])).astype(np.float32),
+                       cov=np.concatenate([a.cov, b.cov]), width=W, height=H)
+    G = synth.image_grad(W, H, 29)
+    cfg = R.RasterConfig(reduce_mode="tile")
+    ws = R.Workspace()
+    p = R.prepare_2d(t(s.means2d), t(s.conics), t(s.opacities), t(s.rgb), t(s.depth), W, H, cfg, ws)
+    R.raster_setup(p, cfg, ws)
+    f = R.raster_forward(p, cfg, ws, reuse_setup=True)               # split + merge
+    bw = R.raster_backward(p, f["fb"], t(G), cfg, ws, live=True, reuse_setup=True)
+    f2 = R.raster_forward(p, cfg, ws, coverage=True, reuse_setup=True)   # one pass per tile
+    torch.cuda.synchronize()
+    img, T = f["image"].cpu().numpy(), f["T"].cpu().numpy()
+    assert np.abs(img - f2["image"].cpu().numpy()).max() <= 2e-6
+    assert np.abs(T - f2["T"].cpu().numpy()).max() <= 2e-6
+    ref = _oracle(s, W, H, G, oracle.OracleConfig(**BAND))
+    e = _check(dict(img=img, T=T, cov=f2["coverage"].cpu().numpy(), live=bw["live"].cpu().numpy(),
+                    grad=grads9(bw)), ref)
+    print("depth split:", e, "covered/px at the centre", ref["cov"][76:116, 104:152].mean())
+    assert ref["cov"][76:116, 104:152].mean() > 200
+
+
 def test_shared_setup_matches_per_call_setup():
     """gs_raster_setup once + GS_FLAG_REUSE_SETUP on the forward and the backward gives what
     each call building its own setup gives, and matches the oracle; a workspace that held another
