@@ -166,7 +166,7 @@ size_t gs_framebuffer_size(int32_t width, int32_t height, int32_t fb_format);
  * covariance is not positive definite, or the bounding box of its alpha >= alpha_min ellipse
  * holds no pixel centre of the image.
  * Inputs [n]: means3d [n,3], scales [n,3], quats [n,4], opacities [n] (in [0,1]),
- *   sh [n, (sh_degree+1)^2, 3].
+ *   sh [n, (sh_degree+1)^2, 3] (16-byte aligned; GS_ERR_INVALID_ARGUMENT otherwise).
  * Outputs by splat id: means2d [n,2], conics [n,3], rgb [n,3], depth [n] (fp32 view depth; 0 if
  *   culled; culled splats also get zero means2d/conics/rgb).
  * Sort input (GPU-driven culling, Sec. 4.1): keys [n], ids [n] hold the visible splats first, in
@@ -271,7 +271,8 @@ int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
  * the view-direction term of the SH colour and the quaternion normalisation. Recomputes the
  * forward from the same inputs as gs_preprocess. Culled splats get zero gradients.
  * Outputs (overwritten): dL_dmeans3d [n,3], dL_dscales [n,3], dL_dquats [n,4],
- *   dL_dopacities [n], dL_dsh [n,(sh_degree+1)^2,3]. Workspace: none.
+ *   dL_dopacities [n], dL_dsh [n,(sh_degree+1)^2,3]. sh and dL_dsh must be 16-byte aligned.
+ *   Workspace: none.
  */
 int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
                       const float* means3d, const float* scales, const float* quats,

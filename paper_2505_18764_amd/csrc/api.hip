@@ -110,6 +110,12 @@ int check_ws(void* ws, size_t have, size_t need) {
     return GS_OK;
 }
 
+int check_align16(const void* p, const char* what) {
+    if (((uintptr_t)p) % 16 != 0)
+        return fail(GS_ERR_INVALID_ARGUMENT, "%s must be 16-byte aligned", what);
+    return GS_OK;
+}
+
 size_t preprocess_ws(int32_t n) { return gsr::align_up((size_t)n * 4) + gsr::compact_ws_bytes(n); }
 
 }  // namespace
@@ -177,6 +183,7 @@ int gs_preprocess(const gs_camera* cam, const gs_config* cfg, int32_t n, const f
         GSR_NEED(means3d); GSR_NEED(scales); GSR_NEED(quats); GSR_NEED(opacities); GSR_NEED(sh);
         GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(rgb); GSR_NEED(depth); GSR_NEED(keys);
         GSR_NEED(ids);
+        GSR_TRY(check_align16(sh, "sh"));
         GSR_TRY(check_ws(ws, ws_bytes, preprocess_ws(n)));
     }
     const gsr::CamDev cd = gsr::make_cam(*cam);
@@ -295,6 +302,8 @@ int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, con
     GSR_NEED(dL_dmeans2d); GSR_NEED(dL_dconics); GSR_NEED(dL_drgb); GSR_NEED(dL_dopacities2d);
     GSR_NEED(dL_dmeans3d); GSR_NEED(dL_dscales); GSR_NEED(dL_dquats); GSR_NEED(dL_dopacities);
     GSR_NEED(dL_dsh);
+    GSR_TRY(check_align16(sh, "sh"));
+    GSR_TRY(check_align16(dL_dsh, "dL_dsh"));
     const gsr::CamDev cd = gsr::make_cam(*cam);
     return hip_status(gsr::launch_preprocess_bwd(cd, *cfg, n, means3d, scales, quats, opacities, sh,
                                                  dL_dmeans2d, dL_dconics, dL_drgb, dL_dopacities2d,

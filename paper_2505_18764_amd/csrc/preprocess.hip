@@ -172,12 +172,44 @@ __device__ __forceinline__ void geometry(const CamDev& cam, float amin, float ep
     }
 }
 
+// The NC = 3 (deg + 1)^2 SH coefficients of one Gaussian between memory and registers. With NC a
+// multiple of 4 (degrees 1 and 3) every Gaussian's block starts 16-byte aligned, and one wave
+// instruction moves 64 x 16 B instead of 64 x 4 B at a stride of NC floats.
+template <int NC>
+__device__ __forceinline__ void load_coeffs(const float* __restrict__ p, float (&c)[NC]) {
+    if constexpr (NC % 4 == 0) {
+        const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+        for (int j = 0; j < NC / 4; ++j) {
+            const float4 v = q[j];
+            c[4 * j] = v.x; c[4 * j + 1] = v.y; c[4 * j + 2] = v.z; c[4 * j + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) c[j] = p[j];
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void store_coeffs(float* __restrict__ p, const float (&c)[NC]) {
+    if constexpr (NC % 4 == 0) {
+        float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+        for (int j = 0; j < NC / 4; ++j) q[j] = make_float4(c[4 * j], c[4 * j + 1], c[4 * j + 2], c[4 * j + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) p[j] = c[j];
+    }
+}
+
+template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(
     int n, const float* __restrict__ means3d, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
-    int deg, CamDev cam, float amin, float eps2d, float* __restrict__ means2d,
+    CamDev cam, float amin, float eps2d, float* __restrict__ means2d,
     float* __restrict__ conics, float* __restrict__ rgb, float* __restrict__ depth,
     uint32_t* __restrict__ key_by_id) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         bool vis = false;
@@ -194,10 +226,11 @@ __global__ __launch_bounds__(256) void k_preprocess(
             const float il = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
             vx *= il; vy *= il; vz *= il;
             float Y[16];
-            sh_eval(vx, vy, vz, deg, Y);
-            const int K = (deg + 1) * (deg + 1);
-            const float* c = sh + (size_t)i * K * 3;
+            sh_eval(vx, vy, vz, DEG, Y);
+            float c[3 * K];
+            load_coeffs<3 * K>(sh + (size_t)i * (3 * K), c);
             c0 = 0.5f; c1 = 0.5f; c2 = 0.5f;
+#pragma unroll
             for (int k = 0; k < K; ++k) {
                 c0 += Y[k] * c[3 * k];
                 c1 += Y[k] * c[3 * k + 1];
@@ -218,16 +251,17 @@ __global__ __launch_bounds__(256) void k_preprocess(
     }
 }
 
+template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     int n, const float* __restrict__ means3d, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
-    int deg, CamDev cam, float amin, float eps2d, const float* __restrict__ g_m2,
+    CamDev cam, float amin, float eps2d, const float* __restrict__ g_m2,
     const float* __restrict__ g_con, const float* __restrict__ g_rgb,
     const float* __restrict__ g_op2, float* __restrict__ d_m3, float* __restrict__ d_sc,
     float* __restrict__ d_q, float* __restrict__ d_op, float* __restrict__ d_sh) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int K = (deg + 1) * (deg + 1);
+    constexpr int K = (DEG + 1) * (DEG + 1);
     const float o = opac[i];
     Geo g;
     geometry(cam, amin, eps2d, cam.width, cam.height, means3d + 3 * (size_t)i,
@@ -237,7 +271,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         for (int j = 0; j < 3; ++j) { d_m3[3 * (size_t)i + j] = 0.f; d_sc[3 * (size_t)i + j] = 0.f; }
         for (int j = 0; j < 4; ++j) d_q[4 * (size_t)i + j] = 0.f;
         d_op[i] = 0.f;
-        for (int j = 0; j < 3 * K; ++j) dsh[j] = 0.f;
+        float z[3 * K];
+#pragma unroll
+        for (int j = 0; j < 3 * K; ++j) z[j] = 0.f;
+        store_coeffs<3 * K>(dsh, z);
         return;
     }
     // ---- conic -> Sigma_2D: G2 = -C Ghat C, Ghat = [[ga, gb/2], [gb/2, gc]] ----------------
@@ -317,22 +354,27 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float il = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
     const float ux = vx * il, uy = vy * il, uz = vz * il;
     float Y[16];
-    sh_eval(ux, uy, uz, deg, Y);
-    const float* co = sh + (size_t)i * K * 3;
+    sh_eval(ux, uy, uz, DEG, Y);
+    float co[3 * K];
+    load_coeffs<3 * K>(sh + (size_t)i * (3 * K), co);
     float val[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
     for (int k = 0; k < K; ++k)
         for (int ch = 0; ch < 3; ++ch) val[ch] += Y[k] * co[3 * k + ch];
     float gv[3];
     for (int ch = 0; ch < 3; ++ch) gv[ch] = val[ch] > 0.f ? g_rgb[3 * (size_t)i + ch] : 0.f;
-    float wY[16];
+    float wY[16], dc[3 * K];
+#pragma unroll
     for (int k = 0; k < K; ++k) {
-        dsh[3 * k] = gv[0] * Y[k];
-        dsh[3 * k + 1] = gv[1] * Y[k];
-        dsh[3 * k + 2] = gv[2] * Y[k];
+        dc[3 * k] = gv[0] * Y[k];
+        dc[3 * k + 1] = gv[1] * Y[k];
+        dc[3 * k + 2] = gv[2] * Y[k];
         wY[k] = gv[0] * co[3 * k] + gv[1] * co[3 * k + 1] + gv[2] * co[3 * k + 2];
     }
+    store_coeffs<3 * K>(dsh, dc);
+#pragma unroll
     for (int k = K; k < 16; ++k) wY[k] = 0.f;
-    const float3 gd = sh_grad_dir(ux, uy, uz, deg, wY);
+    const float3 gd = sh_grad_dir(ux, uy, uz, DEG, wY);
     const float dd = gd.x * ux + gd.y * uy + gd.z * uz;
     dmx += (gd.x - ux * dd) * il;
     dmy += (gd.y - uy * dd) * il;
@@ -407,9 +449,11 @@ hipError_t launch_preprocess(const CamDev& cam, const gs_config& cfg, int n, con
     if (n == 0) return launch_fill_u32(n_visible, 1, 0u, s);
     uint32_t* key_by_id = (uint32_t*)ws;
     void* rest = (char*)ws + align_up((size_t)n * 4);
-    hipLaunchKernelGGL(k_preprocess, dim3((n + 255) / 256), dim3(256), 0, s, n, means3d, scales,
-                       quats, opac, sh, cfg.sh_degree, cam, cfg.alpha_min, cfg.eps2d, means2d,
-                       conics, rgb, depth, key_by_id);
+    decltype(&k_preprocess<3>) k = cfg.sh_degree == 0 ? k_preprocess<0>
+                                  : cfg.sh_degree == 1 ? k_preprocess<1>
+                                  : cfg.sh_degree == 2 ? k_preprocess<2> : k_preprocess<3>;
+    hipLaunchKernelGGL(k, dim3((n + 255) / 256), dim3(256), 0, s, n, means3d, scales, quats, opac,
+                       sh, cam, cfg.alpha_min, cfg.eps2d, means2d, conics, rgb, depth, key_by_id);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_compact(n, key_by_id, keys, ids, n_visible, rest, s);
@@ -422,10 +466,12 @@ hipError_t launch_preprocess_bwd(const CamDev& cam, const gs_config& cfg, int n,
                                  float* d_means3d, float* d_scales, float* d_quats, float* d_opac,
                                  float* d_sh, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3((n + 255) / 256), dim3(256), 0, s, n, means3d,
-                       scales, quats, opac, sh, cfg.sh_degree, cam, cfg.alpha_min, cfg.eps2d,
-                       g_means2d, g_conics, g_rgb, g_opac2d, d_means3d, d_scales, d_quats, d_opac,
-                       d_sh);
+    decltype(&k_preprocess_bwd<3>) k = cfg.sh_degree == 0 ? k_preprocess_bwd<0>
+                                      : cfg.sh_degree == 1 ? k_preprocess_bwd<1>
+                                      : cfg.sh_degree == 2 ? k_preprocess_bwd<2> : k_preprocess_bwd<3>;
+    hipLaunchKernelGGL(k, dim3((n + 255) / 256), dim3(256), 0, s, n, means3d, scales, quats, opac,
+                       sh, cam, cfg.alpha_min, cfg.eps2d, g_means2d, g_conics, g_rgb, g_opac2d,
+                       d_means3d, d_scales, d_quats, d_opac, d_sh);
     return hipGetLastError();
 }
 

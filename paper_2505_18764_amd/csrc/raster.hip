@@ -8,12 +8,14 @@
 //     made of four 8x8 sub-blocks; lane l holds the same position in each sub-block, and lanes
 //     4k..4k+3 form a 2x2 pixel quad, so DPP quad_perm is the paper's quad;
 //   * the workgroup walks the globally depth-sorted splat array in order (no per-tile lists,
-//     memory O(N + pixels)): each fill, its waves test 4096 consecutive splats' tile rectangles,
-//     compact the hits in order into LDS, stage their records in LDS, and then every wave applies
-//     the staged splats one after another to its own pixels, whose state lives in VGPRs. A pixel
-//     is only ever touched by one lane, in splat order, so no interlock is needed;
-//   * a splat is skipped for a sub-block its pixel bounding box misses (one scalar branch).
-// Each fill iteration therefore processes one splat per wave across up to 64 lanes; that is the
+//     memory O(N + pixels)) in rounds of up to 64 chunks of 64 sorted splats that the tile's
+//     occupancy bitmap marks; the waves test the chunks' tile rectangles, compact the hits in
+//     order into LDS and stage their records in LDS; every wave then applies the staged splats
+//     one after another to its own pixels, whose state lives in VGPRs. A pixel is only ever
+//     touched by one lane, in splat order, so no interlock is needed;
+//   * per staged batch, each wave keeps only the splats whose alpha can reach alpha_min in one
+//     of its sub-blocks, with a mask of those sub-blocks.
+// Each iteration therefore processes one splat per wave across up to 64 lanes; that is the
 // "subgroup" of Procedure 2, and its live lanes always share one splat id (cohesion 100 %).
 #include "device.hpp"
 #include "internal.hpp"
@@ -21,8 +23,7 @@
 namespace gsr {
 
 constexpr int NT = 256;            // threads per workgroup
-constexpr int SPAN = 1024;         // sorted splats one wave tests per fill
-constexpr int CHUNK = 4 * SPAN;    // sorted splats the workgroup tests per fill
+constexpr int SPAN = 1024;         // hits one wave can hold per round (16 chunks of 64 splats)
 constexpr int BATCH = 256;         // splat records staged in LDS at once
 
 // A staged splat: a = (mean x, mean y, a', k); b = (d', opacity, r, g);
@@ -330,10 +331,17 @@ __global__ __launch_bounds__(256) void k_raster_setup(
         }
 }
 
-// ---- the shared walk: scan 4096 sorted splats, compact hits in order, stage records ----------
+// ---- the shared walk ------------------------------------------------------------------------
+// Rounds of up to 64 occupied chunks (chunk = 64 consecutive sorted splats; occupied = its bit is
+// set in the tile's occupancy bitmap). Wave w tests the splats of the round's chunks
+// [16 w, 16 w + 16) against the tile, so the four waves' hit lists concatenate in sorted order;
+// the hits are staged into LDS in batches. A dense tile's round is 4096 consecutive splats; a
+// sparse tile skips the chunks none of whose splats touch it, so its walk takes few rounds.
 struct Walk {
-    uint16_t seg[4][SPAN];
+    uint16_t seg[4][SPAN];      // per wave: hits as chunk slot << 6 | lane
     uint16_t list[4][BATCH];
+    int chunk[64];              // the round's chunks, increasing
+    int nchunk;
     int segn[4];
     int alive[4];
     Rec rec[BATCH];
@@ -379,47 +387,81 @@ __device__ __forceinline__ int cull_batch(Walk& w, int m, int wave, int lane, ui
     return cnt;
 }
 
-// Tests the wave's 1024 splats of this fill against the tile, one 64-splat chunk per set bit of
-// `chunks` (16 bits, from the occupancy bitmap); writes the in-order offsets of the hits to
-// w.seg[wave] and their count to w.segn[wave].
-__device__ __forceinline__ void scan_span(Walk& w, const uint2* __restrict__ rect, int wb, int nvis,
-                                          uint32_t ttx, uint32_t tty, int wave, int lane,
-                                          uint64_t lt, uint32_t chunks) {
+// Wave 0: the next (up to) 64 occupied chunks in [cursor, cend) into w.chunk / w.nchunk, and the
+// cursor moved past them (every chunk counts as occupied without a bitmap). One bitmap word per
+// lane; a wave prefix sum of the words' popcounts places each lane's chunks.
+__device__ __forceinline__ void next_round(Walk& w, const uint32_t* __restrict__ trow, int cend,
+                                           int lane, int& cursor) {
+    int cc = cursor, got = 0;
+    if (!trow) {
+        got = min(64, max(0, cend - cc));
+        if (lane < got) w.chunk[lane] = cc + lane;
+        cc += got;
+    } else {
+        while (got < 64 && cc < cend) {
+            const int wi = (cc >> 5) + lane;
+            uint32_t word = wi * 32 < cend ? trow[wi] : 0u;
+            if (lane == 0) word &= ~0u << (cc & 31);           // chunks before the cursor
+            const int left = cend - wi * 32;                   // chunks from cend on
+            if (left < 32) word &= left > 0 ? (1u << left) - 1u : 0u;
+            const int pc = popc(word);
+            int incl = pc;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o);
+                if (lane >= o) incl += u;
+            }
+            const int excl = incl - pc, need = 64 - got;
+            const int take = max(0, min(pc, need - excl));
+            int last = -1;
+            for (int t = 0; t < take; ++t) {
+                const int bit = __builtin_ctz(word);
+                word &= word - 1u;
+                last = wi * 32 + bit;
+                w.chunk[got + excl + t] = last;
+            }
+            const int total = __shfl(incl, 63);
+            if (total >= need) {                              // the round is full
+                const uint64_t edge = ballot(excl < need && incl >= need);
+                cc = __shfl(last, (int)__builtin_ctzll(edge)) + 1;
+                got = 64;
+            } else {
+                got += total;
+                cc = ((cc >> 5) + 64) * 32;                    // all 64 words consumed
+            }
+        }
+    }
+    cursor = cc;
+    if (lane == 0) w.nchunk = got;
+}
+
+// Wave `wave`: tests the splats of the round's chunk slots [16 wave, 16 wave + 16) against the
+// tile; writes the in-order hits to w.seg[wave] (slot << 6 | lane) and their count to w.segn.
+__device__ __forceinline__ void scan_round(Walk& w, const uint2* __restrict__ rect, int nvis,
+                                           uint32_t ttx, uint32_t tty, int wave, int lane,
+                                           uint64_t lt) {
     int cnt = 0;
-    if (wb >= nvis) chunks = 0;
-    while (chunks) {
-        const int b0 = __builtin_ctz(chunks);
-        chunks &= chunks - 1u;
-        const int b1 = chunks ? __builtin_ctz(chunks) : -1;   // two chunks per round
-        if (b1 >= 0) chunks &= chunks - 1u;
-        const int o0 = b0 * 64 + lane, o1 = b1 * 64 + lane;
-        const uint2 r0 = wb + o0 < nvis ? rect[wb + o0] : make_uint2(0xFFFFu, 0u);
-        const uint2 r1 = (b1 >= 0 && wb + o1 < nvis) ? rect[wb + o1] : make_uint2(0xFFFFu, 0u);
+    const int s0 = wave * 16, s1 = min(w.nchunk, s0 + 16);
+    for (int sl = s0; sl < s1; sl += 2) {                     // two chunks per step
+        const bool two = sl + 1 < s1;
+        const int o0 = w.chunk[sl] * 64 + lane;
+        const int o1 = two ? w.chunk[sl + 1] * 64 + lane : nvis;
+        const uint2 r0 = o0 < nvis ? rect[o0] : make_uint2(0xFFFFu, 0u);
+        const uint2 r1 = o1 < nvis ? rect[o1] : make_uint2(0xFFFFu, 0u);
         const bool h0 = rect_hit(r0, ttx, tty);
         const uint64_t m0 = ballot(h0);
-        if (h0) w.seg[wave][cnt + popc(m0 & lt)] = (uint16_t)o0;
+        if (h0) w.seg[wave][cnt + popc(m0 & lt)] = (uint16_t)((sl << 6) | lane);
         cnt += popc(m0);
         const bool h1 = rect_hit(r1, ttx, tty);
         const uint64_t m1 = ballot(h1);
-        if (h1) w.seg[wave][cnt + popc(m1 & lt)] = (uint16_t)o1;
+        if (h1) w.seg[wave][cnt + popc(m1 & lt)] = (uint16_t)(((sl + 1) << 6) | lane);
         cnt += popc(m1);
     }
     if (lane == 0) w.segn[wave] = cnt;
 }
 
-// The tile's 64 chunk bits for the fill starting at sorted position `base` (all ones without a
-// bitmap).
-__device__ __forceinline__ uint64_t window_bits(const uint32_t* __restrict__ trow, int wpr, int base) {
-    if (!trow) return ~0ull;
-    const int wi = (base / CHUNK) * 2;
-    const uint32_t lo = wi < wpr ? trow[wi] : 0u;
-    const uint32_t hi = wi + 1 < wpr ? trow[wi + 1] : 0u;
-    return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
-// Stages hits [b0, b0 + BATCH) of the fill (in order across the four waves' segments).
-__device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int base, int b0,
-                                      int total, int tid) {
+// Stages hits [b0, b0 + BATCH) of the round (in order across the four waves' lists).
+__device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int b0, int total,
+                                      int tid) {
     const int e = b0 + tid;
     if (e < total) {
         int off = e, ws = 0;
@@ -430,7 +472,8 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
                 if (off >= w.segn[2]) { off -= w.segn[2]; ws = 3; }
             }
         }
-        const int pos = base + ws * SPAN + w.seg[ws][off];
+        const uint32_t v = w.seg[ws][off];
+        const int pos = w.chunk[v >> 6] * 64 + (int)(v & 63u);
         Rec r = rec[pos];
         r.c.y = (uint32_t)pos;      // the gradient slot comes from the walk, never from memory
         w.rec[tid] = r;
@@ -494,24 +537,22 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     int nvis = *nvis_ptr;
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     uint32_t nq = 0;
-    // sorted positions [p0, p1) of this item; segment bounds are multiples of SETUP_SPAN
-    const int p0 = c_begin * SETUP_SPAN;
-    const int p1 = c_end >= wpr ? nvis : min(nvis, c_end * SETUP_SPAN);
-
+    // chunks [32 c_begin, cend) of this item (a 2048-position column is 32 chunks)
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
-    for (int base = (p0 / CHUNK) * CHUNK; base < p1; base += CHUNK) {
-        uint64_t wbits = window_bits(trow, wpr, base);
-        if (base < p0) wbits &= ~0xFFFFFFFFull;                  // first half before the segment
-        if (p1 <= base + SETUP_SPAN) wbits &= 0xFFFFFFFFull;      // second half after it
-        if (wbits == 0) continue;                 // no splat of this fill touches the tile
-        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt,
-                  (uint32_t)(wbits >> (16 * wave)) & 0xFFFFu);
+    const int nch = (nvis + 63) / 64;
+    const int cend = c_end >= wpr ? nch : min(nch, c_end * 32);
+    int cursor = c_begin * 32;                    // wave 0's position in the walk
+    for (;;) {
+        if (wave == 0) next_round(w, trow, cend, lane, cursor);
+        __syncthreads();
+        if (w.nchunk == 0) break;
+        scan_round(w, rect, nvis, ttx, tty, wave, lane, lt);
         __syncthreads();
         const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
         if (INSTR) nq += total;
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
-            stage(w, rec, base, b0, total, tid);
+            stage(w, rec, b0, total, tid);
             __syncthreads();
             const int m = min(BATCH, total - b0);
             if (!TCULL || alive) {
@@ -783,18 +824,20 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     const bool lane_acc = (mode == GS_REDUCE_HYBRID_LANE || mode == GS_REDUCE_TILE);
 
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
-    for (int base = 0; base < nvis; base += CHUNK) {
-        const uint64_t wbits = window_bits(trow, wpr, base);
-        if (wbits == 0) continue;                 // no splat of this fill touches the tile
-        scan_span(w, rect, base + wave * SPAN, nvis, ttx, tty, wave, lane, lt,
-                  (uint32_t)(wbits >> (16 * wave)) & 0xFFFFu);
+    const int nch = (nvis + 63) / 64;
+    int cursor = 0;                               // wave 0's position in the walk
+    for (;;) {
+        if (wave == 0) next_round(w, trow, nch, lane, cursor);
+        __syncthreads();
+        if (w.nchunk == 0) break;
+        scan_round(w, rect, nvis, ttx, tty, wave, lane, lt);
         __syncthreads();
         const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
         if (INSTR) nq += total;
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
             if (tile_acc) { flush_tile_grad<INSTR>(tg, w, pend, tid, grad, cnt); pend = 0; }
-            stage(w, rec, base, b0, total, tid);
+            stage(w, rec, b0, total, tid);
             __syncthreads();
             const int m = min(BATCH, total - b0);
             pend = m;

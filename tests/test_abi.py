@@ -113,6 +113,10 @@ def test_invalid_arguments_rejected_on_host():
     assert L.lib().gs_preprocess(ctypes.byref(cam), ctypes.byref(cfg), 5, None, None, None, None,
                                  None, None, None, None, None, None, None, fake, ws, 1 << 20,
                                  None) == 1
+    f = fake
+    assert L.lib().gs_preprocess(ctypes.byref(cam), ctypes.byref(cfg), 5, f, f, f, f, f + 4, f, f, f,
+                                 f, f, f, f, ws, 1 << 20, None) == 1
+    assert "aligned" in L.gs_last_error()                  # sh: 16-byte aligned
     cz = _cam(L)
     cz.znear = 0.0
     assert L.lib().gs_preprocess_bwd(ctypes.byref(cz), ctypes.byref(cfg), 0, *([None] * 14),
