@@ -45,27 +45,33 @@ def _parse():
                     help="requests of the serving run (0: skip); 100 more are warmup")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="write profiles/traffic.json from DIR/{fetch,write,cfetch,cwrite} "
+                         "rocprofv3 databases (no GPU work)")
     return ap.parse_args()
 
 
-def _src_hash():
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2505_18764_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2505_18764_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def _traffic(kernel_key):
-    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they match this build."""
+def _traffic(kernels):
+    """HBM bytes per launch of the given kernels (summed) from the committed PMC summary, if it
+    was taken with the current kernel sources; else None."""
+    from paper_2505_18764_amd import pmc
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    e = d.get(kernel_key)
-    if not e or e.get("source_hash") != _src_hash():
-        return None
-    return e.get("bytes_per_launch")
+    h = pmc.source_hash()
+    tot = 0.0
+    for k in kernels:
+        e = d.get(k)
+        if not e or e.get("source_hash") != h:
+            return None
+        tot += e["bytes_per_launch"]
+    return tot
+
+
+# the launches of the timed raster stages (paper mode, FP16 at rest, no counters)
+FWD_KERNELS = ("k_raster_fwd<-1, false, false>", "k_raster_merge")
+BWD_KERNELS = ("k_raster_bwd<-1, false>",)
 
 
 def main():
@@ -74,6 +80,23 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the path has no multi-GPU "
               "component; views are independent and would shard one view per GPU.", file=sys.stderr)
         sys.exit(2)
+    if args.summarize_pmc:
+        from paper_2505_18764_amd import pmc
+        d = args.summarize_pmc
+        B = "python -u bench.py --steps 3 --warmup 1 --no-cpu --no-tile --serve-requests 0 --formats f16"
+        cmd = "\n".join([
+            "cd /tmp && export TMPDIR=/tmp && R=<repository root>",
+            f"rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $OUT/fetch -o run -- {B.replace('bench.py', '$R/bench.py')}",
+            f"rocprofv3 --pmc WRITE_SIZE --kernel-trace -d $OUT/write -o run -- {B.replace('bench.py', '$R/bench.py')}",
+            "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $OUT/cfetch -o run -- python -u $R/bench.py --copy-probe",
+            "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d $OUT/cwrite -o run -- python -u $R/bench.py --copy-probe",
+            "python bench.py --summarize-pmc $OUT"])
+        res = pmc.summarize(os.path.join(d, "fetch"), os.path.join(d, "write"),
+                            os.path.join(d, "cfetch"), os.path.join(d, "cwrite"), 512 << 20,
+                            os.path.join(ROOT, "profiles"), cmd,
+                            "1M clustered Gaussians, 1600x1064, FP16 framebuffer")
+        print(json.dumps({k: v for k, v in res.items() if k.startswith("_")}))
+        return
     import torch
     import synth
     from paper_2505_18764_amd import render as R
@@ -200,12 +223,14 @@ def main():
     F, Lv = st["fwd_covered"], st["bwd_live"]
     fwd_ms, bwd_ms = head["stages_ms"]["raster_fwd"], head["stages_ms"]["raster_bwd"]
     roof = {}
-    for name, ms, flops, key in (("raster_fwd", fwd_ms, F * FLOP_FWD_PER_COVERED, "k_raster_fwd"),
-                                 ("raster_bwd", bwd_ms, Lv * FLOP_BWD_PER_LIVE, "k_raster_bwd")):
+    for name, ms, flops, keys in (("raster_fwd", fwd_ms, F * FLOP_FWD_PER_COVERED, FWD_KERNELS),
+                                  ("raster_bwd", bwd_ms, Lv * FLOP_BWD_PER_LIVE, BWD_KERNELS)):
         ach = flops / (ms * 1e-3) / 1e12
+        tr = _traffic(keys) if head_fmt == "f16" else None
         roof[name] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
                       "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                      "traffic": _traffic(key), "flops_per_launch": flops, "ms": round(ms, 4)}
+                      "traffic": None if tr is None else round(tr), "flops_per_launch": flops,
+                      "ms": round(ms, 4), "kernels": list(keys)}
     dom = "raster_fwd" if fwd_ms >= bwd_ms else "raster_bwd"
 
     extra = {}

@@ -1,0 +1,113 @@
+"""HBM traffic per kernel launch from rocprofv3 PMC databases.
+
+Two counter passes over the same program, one with ``--pmc FETCH_SIZE`` and one with
+``--pmc WRITE_SIZE`` (each with ``--kernel-trace``), give per-dispatch kilobytes read from and
+written to device memory. The counters' scale is calibrated against a plain device-to-device
+copy of known size (``bench.py --copy-probe``, 512 MiB copied three times), profiled the same
+two ways: the calibration factor of each counter is bytes copied / (counter KiB x 1024).
+
+``summarize`` writes ``traffic.json`` (per kernel: scaled bytes read, written, and their sum per
+launch, the mean launch duration, and the hash of the kernel sources the counters were taken
+with; a consumer ignores entries whose hash differs from the current sources) and a short
+markdown table.
+"""
+from __future__ import annotations
+
+import collections
+import hashlib
+import json
+import os
+import re
+import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources (the counters describe the kernels these sources build)."""
+    h = hashlib.sha256()
+    d = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(n: str) -> str:
+    n = re.sub(r"\(.*$", "", n)
+    return n.replace("void ", "").replace("gsr::", "").strip()
+
+
+def _db(path: str) -> str:
+    if os.path.isdir(path):
+        for root, _, files in os.walk(path):
+            for f in files:
+                if f.endswith("_results.db"):
+                    return os.path.join(root, f)
+        raise FileNotFoundError(f"no *_results.db under {path}")
+    return path
+
+
+def counter_means(path: str) -> dict:
+    """{kernel: {counter: mean value per dispatch, '_calls': n, '_dur_ns': mean duration}}."""
+    cur = sqlite3.connect(_db(path)).cursor()
+    vals = collections.defaultdict(lambda: collections.defaultdict(dict))
+    dur = collections.defaultdict(dict)
+    for k, c, v, d, du in cur.execute(
+            "select kernel_name, counter_name, value, dispatch_id, duration from counters_collection"):
+        k = short_name(k)
+        vals[k][c][d] = vals[k][c].get(d, 0.0) + float(v)
+        dur[k][d] = float(du)
+    out = {}
+    for k, cs in vals.items():
+        out[k] = {c: sum(dv.values()) / len(dv) for c, dv in cs.items()}
+        out[k]["_calls"] = len(dur[k])
+        out[k]["_dur_ns"] = sum(dur[k].values()) / max(1, len(dur[k]))
+    return out
+
+
+def _copy_kernel(m: dict) -> str:
+    cands = [k for k in m if "copy" in k.lower()]
+    if not cands:
+        raise ValueError("no copy kernel in the calibration database")
+    return max(cands, key=lambda k: m[k]["_dur_ns"])
+
+
+def summarize(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes: int, out_dir: str,
+              command: str, workload: str) -> dict:
+    f, w = counter_means(fetch_db), counter_means(write_db)
+    cf, cw = counter_means(copy_fetch_db), counter_means(copy_write_db)
+    kf, kw = _copy_kernel(cf), _copy_kernel(cw)
+    fac_f = copy_bytes / (cf[kf]["FETCH_SIZE"] * 1024.0)
+    fac_w = copy_bytes / (cw[kw]["WRITE_SIZE"] * 1024.0)
+    h = source_hash()
+    res = {"_calibration": {"copy_bytes": copy_bytes, "fetch_factor": fac_f, "write_factor": fac_w,
+                            "copy_kernel": kf},
+           "_command": command, "_workload": workload}
+    for k in sorted(set(f) & set(w)):
+        if "FETCH_SIZE" not in f[k] or "WRITE_SIZE" not in w[k]:
+            continue
+        rd = f[k]["FETCH_SIZE"] * 1024.0 * fac_f
+        wr = w[k]["WRITE_SIZE"] * 1024.0 * fac_w
+        res[k] = {"read_bytes": rd, "write_bytes": wr, "bytes_per_launch": rd + wr,
+                  "mean_ns": f[k]["_dur_ns"], "calls": f[k]["_calls"], "source_hash": h}
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
+        json.dump(res, fh, indent=1)
+    lines = [f"# HBM traffic per launch: {workload}", "",
+             "Commands (run from the repository root on one MI355X; `$OUT` is any scratch "
+             "directory):", "", "```", command, "```", "",
+             f"Calibration: a {copy_bytes / 2**20:.0f} MiB device copy reads FETCH_SIZE x "
+             f"{fac_f:.3f} and WRITE_SIZE x {fac_w:.3f} (bytes per counter byte).", "",
+             "| kernel | calls | mean us | read MB | written MB | GB/s |", "|---|---:|---:|---:|---:|---:|"]
+    for k, v in sorted(((k, v) for k, v in res.items() if not k.startswith("_")),
+                       key=lambda kv: -kv[1]["mean_ns"] * kv[1]["calls"]):
+        if v["mean_ns"] * v["calls"] < 20_000:
+            continue
+        gbs = v["bytes_per_launch"] / v["mean_ns"]
+        lines.append(f"| `{k}` | {v['calls']} | {v['mean_ns'] / 1e3:.1f} | {v['read_bytes'] / 1e6:.1f} | "
+                     f"{v['write_bytes'] / 1e6:.1f} | {gbs:.0f} |")
+    lines += ["", f"Source hash of the kernels measured: `{h}`."]
+    with open(os.path.join(out_dir, "traffic_1M_1600x1064_f16.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return res
