@@ -42,12 +42,12 @@ struct RasterWs {
     // count and first item, and FP32 partial states of the split tiles' segments
     int split;
     uint16_t* colcnt;  // [tiles][wpr]
-    int4* items;       // [2 tiles]
-    uint32_t* item_w;  // [2 tiles]
-    int32_t* item_order; // [2 tiles], -1 past the item count
+    int4* items;       // [4 tiles]
+    uint32_t* item_w;  // [4 tiles]
+    int32_t* item_order; // [4 tiles], -1 past the item count
     int32_t* tile_first; // [tiles]
     int32_t* tile_k;     // [tiles]
-    float4* partial;     // [2 tiles][TILE * TILE]
+    float4* partial;     // [4 tiles][TILE * TILE]
 };
 size_t raster_ws_bytes(int n, int width, int height, bool bwd);
 RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd);

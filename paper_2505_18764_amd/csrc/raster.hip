@@ -64,10 +64,14 @@ constexpr size_t BITMAP_BUDGET = 256u << 20;  // the bitmap is skipped above thi
 // carrying about the same number of splats (from exact per-column counts); each segment is a
 // work item that composites from (0, 1) into an FP32 partial state, and k_raster_merge combines
 // the segments in depth order. Only the at-rest, non-T-culled forward splits: T-culling and
-// per-fragment rounding of the stored state need the segments' inputs in sequence.
+// per-fragment rounding of the stored state need the segments' inputs in sequence. Shorter
+// segments also keep each FP32 colour sum short.
 constexpr int NBUCKETS = 1024;
-constexpr int MAX_SEGMENTS = 8;
+constexpr int MAX_SEGMENTS = 32;
 constexpr int MAX_SPLIT_TILES = 4096;
+// Segment size: a third of the mean tile weight, so sum_t k_t <= 3 ntiles + ntiles.
+constexpr int SEG_DIV = 3;
+constexpr int ITEMS_PER_TILE = SEG_DIV + 1;
 
 // out[0 .. count) = indices ordered by decreasing bucket of w (one workgroup of 1024 threads);
 // out[count .. pad) = -1.
@@ -126,8 +130,11 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
     bucket_order(weights, ntiles, wmax, order, ntiles, s_hist);
     if (!split) return;
     __syncthreads();
-    // k_t with cap = ceil(mean weight): sum of k_t <= total / cap + ntiles <= 2 ntiles
-    const unsigned long long cap = max(1ull, (total + ntiles - 1) / (unsigned long long)ntiles);
+    // k_t = ceil(w_t / cap), cap = ceil(mean weight / SEG_DIV): sum of k_t <= total / cap +
+    // ntiles <= ITEMS_PER_TILE ntiles
+    const unsigned long long cap =
+        max(1ull, (total + (unsigned long long)SEG_DIV * ntiles - 1) /
+                      ((unsigned long long)SEG_DIV * ntiles));
     // exclusive scan of k_t over tiles: thread tid owns tiles [4 tid, 4 tid + 4) (ntiles <= 4096)
     int kk[4], loc = 0;
 #pragma unroll
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
     const int t = blockIdx.x, lane = threadIdx.x;
     const int k = tile_k[t], f = tile_first[t];
     const uint32_t w = weights[t];
-    if (k < 1 || f < 0 || f + k > 2 * ntiles) return;
+    if (k < 1 || f < 0 || f + k > ITEMS_PER_TILE * ntiles) return;
     if (k == 1) {
         if (lane == 0) { items[f] = make_int4(t, 0, wpr, -1); item_w[f] = w; }
         return;
@@ -220,7 +227,7 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_items(
     int32_t* __restrict__ item_order) {
     __shared__ uint32_t s_hist[NBUCKETS];
     __shared__ uint32_t s_max;
-    const int cap = 2 * ntiles;
+    const int cap = ITEMS_PER_TILE * ntiles;
     const int count = (int)min((unsigned long long)cap, counters[0]);
     if (threadIdx.x == 0) s_max = 0u;
     __syncthreads();
@@ -484,8 +491,10 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
 // One workgroup per work item: a whole tile (items == nullptr: block b takes tile order[b]) or,
 // in the depth-split forward, one depth segment of a tile (columns [c_begin, c_end) of 2048
 // sorted positions), which writes its FP32 (C, T) to partial[slot] instead of the framebuffer.
+// Occupancy: LDS (22.8 KB per workgroup) allows 7 workgroups per CU; the second bound asks the
+// compiler for 7 waves per SIMD (<= 72 VGPRs), which measured faster than 6 with fewer spills.
 template <int RFMT, bool TCULL, bool INSTR>
-__global__ __launch_bounds__(NT) void k_raster_fwd(
+__global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
     const uint2* __restrict__ rect, const int32_t* __restrict__ order,
     const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x, int ntiles,
@@ -498,10 +507,10 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     int tile, c_begin = 0, c_end = wpr, slot = -1;
     if (items) {
         const int it = item_order[blockIdx.x];
-        if (it < 0 || it >= 2 * ntiles) return;               // past the item count
+        if (it < 0 || it >= ITEMS_PER_TILE * ntiles) return;      // past the item count
         const int4 v = items[it];
         tile = v.x; c_begin = v.y; c_end = v.z; slot = v.w;
-        if ((unsigned)tile >= (unsigned)ntiles || slot >= 2 * ntiles) return;
+        if ((unsigned)tile >= (unsigned)ntiles || slot >= ITEMS_PER_TILE * ntiles) return;
     } else {
         tile = order[blockIdx.x];
         if ((unsigned)tile >= (unsigned)ntiles) tile = (int)blockIdx.x;   // a schedule not built for this grid
@@ -515,10 +524,7 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
     const uint64_t lt = mask_lt(lane);
     const float cx0 = (float)wx0 + 4.f, cy0 = (float)wy0 + 4.f;   // centre of sub-block 0
 
-    // C accumulates Eq. 2; with the state kept on chip, each staged batch's contributions are
-    // first summed in Cb and folded into C at the batch end, so deep pixels (thousands of
-    // fragments) take far fewer full-magnitude FP32 additions.
-    float px[4], py[4], C[4][3], Cb[4][3], T[4];
+    float px[4], py[4], C[4][3], T[4];
     bool valid[4];
     uint32_t nev[4], ncov[4];
     uint32_t alive = 0;
@@ -529,7 +535,6 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
         px[s] = (float)X + 0.5f;
         py[s] = (float)Y + 0.5f;
         C[s][0] = C[s][1] = C[s][2] = 0.f;
-        Cb[s][0] = Cb[s][1] = Cb[s][2] = 0.f;
         T[s] = 1.f;
         nev[s] = ncov[s] = 0;
         if (ballot(valid[s])) alive |= 1u << s;
@@ -574,15 +579,9 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
                             if (TCULL) pass = pass && T[s] >= tmin;
                             if (pass) {
                                 const float wt = al * T[s];
-                                if constexpr (RFMT >= 0) {      // a render target stores every blend
-                                    C[s][0] = fmaf(wt, B.z, C[s][0]);
-                                    C[s][1] = fmaf(wt, B.w, C[s][1]);
-                                    C[s][2] = fmaf(wt, cb, C[s][2]);
-                                } else {
-                                    Cb[s][0] = fmaf(wt, B.z, Cb[s][0]);
-                                    Cb[s][1] = fmaf(wt, B.w, Cb[s][1]);
-                                    Cb[s][2] = fmaf(wt, cb, Cb[s][2]);
-                                }
+                                C[s][0] = fmaf(wt, B.z, C[s][0]);
+                                C[s][1] = fmaf(wt, B.w, C[s][1]);
+                                C[s][2] = fmaf(wt, cb, C[s][2]);
                                 T[s] = T[s] - wt;                // T (1 - alpha), Eq. 5
                                 if constexpr (RFMT >= 0) {
                                     C[s][0] = fb_round<RFMT>(C[s][0]);
@@ -598,13 +597,6 @@ __global__ __launch_bounds__(NT) void k_raster_fwd(
                             if (TCULL && !ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
                         }
                     }
-                }
-            }
-            if constexpr (RFMT < 0) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    C[s][0] += Cb[s][0]; C[s][1] += Cb[s][1]; C[s][2] += Cb[s][2];
-                    Cb[s][0] = Cb[s][1] = Cb[s][2] = 0.f;
                 }
             }
             if (TCULL && lane == 0) w.alive[wave] = (int)alive;
@@ -660,7 +652,7 @@ __global__ __launch_bounds__(256) void k_raster_merge(
     void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T) {
     const int t = blockIdx.x;
     const int k = tile_k[t], f = tile_first[t];
-    if (k <= 1 || f < 0 || f + k > 2 * ntiles) return;
+    if (k <= 1 || f < 0 || f + k > ITEMS_PER_TILE * ntiles) return;
     const int tx = t % tiles_x, ty = t / tiles_x;
     const size_t P = (size_t)W * H;
     for (int lp = threadIdx.x; lp < TILE * TILE; lp += blockDim.x) {
@@ -1012,8 +1004,9 @@ size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
     size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up(16 * 8) +
                align_up(nt * 4) * 2 + align_up(nt * wpr * 4);
     if (split_ok(n, width, height))
-        b += align_up(nt * wpr * 2) + align_up(2 * nt * 16) + 2 * align_up(2 * nt * 4) +
-             2 * align_up(nt * 4) + align_up(2 * nt * TILE * TILE * 16);
+        b += align_up(nt * wpr * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
+             2 * align_up(ITEMS_PER_TILE * nt * 4) + 2 * align_up(nt * 4) +
+             align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
     if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4);
     return b;
 }
@@ -1034,12 +1027,12 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     r.tile_first = nullptr; r.tile_k = nullptr; r.partial = nullptr;
     if (r.split) {
         r.colcnt = (uint16_t*)p;    p += align_up(nt * (size_t)r.wpr * 2);
-        r.items = (int4*)p;         p += align_up(2 * nt * 16);
-        r.item_w = (uint32_t*)p;    p += align_up(2 * nt * 4);
-        r.item_order = (int32_t*)p; p += align_up(2 * nt * 4);
+        r.items = (int4*)p;         p += align_up(ITEMS_PER_TILE * nt * 16);
+        r.item_w = (uint32_t*)p;    p += align_up(ITEMS_PER_TILE * nt * 4);
+        r.item_order = (int32_t*)p; p += align_up(ITEMS_PER_TILE * nt * 4);
         r.tile_first = (int32_t*)p; p += align_up(nt * 4);
         r.tile_k = (int32_t*)p;     p += align_up(nt * 4);
-        r.partial = (float4*)p;     p += align_up(2 * nt * TILE * TILE * 16);
+        r.partial = (float4*)p;     p += align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
     }
     r.grad = bwd ? (float*)p : nullptr;
     return r;
@@ -1122,7 +1115,8 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
     const bool split = r.split && rfmt < 0 && !tcull && !instr;
     FwdKernel k = tcull ? (instr ? fwd_by_fmt<true, true>(rfmt) : fwd_by_fmt<true, false>(rfmt))
                         : (instr ? fwd_by_fmt<false, true>(rfmt) : fwd_by_fmt<false, false>(rfmt));
-    hipLaunchKernelGGL(k, dim3(split ? 2 * ntiles : ntiles), dim3(NT), 0, s, n, n_visible,
+    hipLaunchKernelGGL(k, dim3(split ? ITEMS_PER_TILE * ntiles : ntiles), dim3(NT), 0, s, n,
+                       n_visible,
                        (const Rec*)r.rec, (const uint2*)r.rect, (const int32_t*)r.order,
                        (const uint32_t*)r.bits, r.wpr, width, height, tiles_x, ntiles,
                        split ? (const int4*)r.items : nullptr,

@@ -63,8 +63,9 @@ def test_sizes_are_closed_forms():
         assert L.gs_workspace_size(op, 1_000_000, 1600, 1064, c) <= allb
     assert L.gs_workspace_size("raster_fwd", -1, 10, 10, c) == 0
     assert L.gs_workspace_size("raster_fwd", 10, 0, 10, c) == 0
-    # fixed O(N + pixels) memory at the 1M / 1600x1064 view: well under 200 MB
-    assert allb < 200 << 20
+    # fixed O(N + pixels) memory at the 1M / 1600x1064 view (records and gradient slots per splat,
+    # bitmap, depth-split partial states): under 256 MiB
+    assert allb < 256 << 20
     assert L.gs_tile_workspace_size(1000, 5000, 128, 128) > L.gs_tile_workspace_size(1000, 0, 128, 128)
 
 
