@@ -70,9 +70,10 @@ enum gs_reduce_mode {
                                    >= X are live, else quad sums */
     GS_REDUCE_HYBRID_LANE = 4,  /* Procedure 2 applied once per splat per wave after each lane
                                    has summed its own pixels' fragments in registers */
-    GS_REDUCE_TILE = 5          /* HYBRID_LANE whose wave sums are added in LDS across the
-                                   workgroup's four waves; one set of global atomics per splat
-                                   and 32x32 tile */
+    GS_REDUCE_TILE = 5          /* per splat and wave, the lanes' register sums are reduced
+                                   over the whole wave at once (nine values through lane swaps;
+                                   no threshold X), the four waves' totals are added in LDS, and
+                                   one set of global atomics per splat and 32x32 tile commits */
 };
 
 enum gs_flags {

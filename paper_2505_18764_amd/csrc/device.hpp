@@ -69,6 +69,49 @@ __device__ __forceinline__ float wave_sum(float v) {
     return read_lane(v, 63);
 }
 
+// ---- nine sums over the wave at once (gfx950 lane swaps) ----------------------------------
+// DPP add source with bound_ctrl set: for the full-mask controls below every lane is valid, so
+// the move fuses into v_add_f32_dpp.
+template <int CTRL>
+__device__ __forceinline__ float dpp_bc(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Every lane of each 16-lane row gets the row's sum.
+__device__ __forceinline__ float row_sum16(float v) {
+    v += dpp_bc<DPP_QUAD_1032>(v);
+    v += dpp_bc<DPP_QUAD_2301>(v);
+    v += dpp_bc<DPP_ROW_HALF_MIRROR>(v);
+    v += dpp_bc<DPP_ROW_MIRROR>(v);
+    return v;
+}
+
+// v_permlane32_swap: a keeps its lanes 0-31 and takes b's lanes 0-31 as lanes 32-63; b receives
+// a's lanes 32-63 as lanes 0-31 and keeps its lanes 32-63. x + y then holds a's sums over the
+// wave halves in lanes 0-31 and b's in lanes 32-63. v_permlane16_swap does the same between
+// adjacent 16-lane rows.
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sums of g[0..8] over the wave (all lanes active), transposed: each pair of values shares a
+// register at every halving step, so 28 VALU instructions replace nine separate reductions.
+// On return every lane of 16-lane row r holds in a the total of g[{0, 2, 1, 3}[r]], in b that of
+// g[{4, 6, 5, 7}[r]], and (row 0) in c that of g[8].
+__device__ __forceinline__ void wave_sum9(const float (&g)[9], float& a, float& b, float& c) {
+    const float p0 = swap32_add(g[0], g[1]), p1 = swap32_add(g[2], g[3]);
+    const float p2 = swap32_add(g[4], g[5]), p3 = swap32_add(g[6], g[7]);
+    const float p4 = swap32_add(g[8], 0.f);
+    a = row_sum16(swap16_add(p0, p1));
+    b = row_sum16(swap16_add(p2, p3));
+    c = row_sum16(swap16_add(p4, 0.f));
+}
+
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 
 // ---- framebuffer formats (Sec. 3.3) -------------------------------------------------------

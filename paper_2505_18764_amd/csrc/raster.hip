@@ -682,11 +682,9 @@ struct BwdCounts {
 
 // Procedure 2 (ReduceGradient) for one splat and one wave: `g` holds this lane's gradient
 // contribution (zero when not live); `gp` is the splat's slot in the accumulation buffer.
-template <bool INSTR, bool TO_LDS = false>
+template <bool INSTR>
 __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* __restrict__ gp,
                                               int mode, int X, int lane, BwdCounts& cnt) {
-    // TO_LDS: gp points into the workgroup's LDS accumulator (the atomics there are ds_add_f32
-    // and the global commit is counted when the accumulator is flushed)
     const uint64_t m = ballot(live);
     if (m == 0) return;
     const int nl = popc(m);
@@ -705,11 +703,8 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
         for (int j = 0; j < 9; ++j) tot[j] = wave_sum(g[j]);
         if (lane == __builtin_ctzll(m))          // subgroupBallotFindLSB(reduceMask)
 #pragma unroll
-            for (int j = 0; j < 9; ++j) {
-                if constexpr (TO_LDS) atomicAdd(gp + j, tot[j]);
-                else atomic_add_f32(gp + j, tot[j]);
-            }
-        if (INSTR && lane == 0) { cnt.sets += TO_LDS ? 0 : 1; cnt.wave_red += 1; cnt.cohesive += 1; }
+            for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, tot[j]);
+        if (INSTR && lane == 0) { cnt.sets += 1; cnt.wave_red += 1; cnt.cohesive += 1; }
         return;
     }
     if (mode == GS_REDUCE_WAVE) {                // standalone subgroup reduction: no quad path
@@ -725,13 +720,10 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
     const bool leader = qm != 0u && (uint32_t)(lane & 3) == (uint32_t)__builtin_ctz(qm | 0x10u);
     if (leader)
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            if constexpr (TO_LDS) atomicAdd(gp + j, g[j]);
-            else atomic_add_f32(gp + j, g[j]);
-        }
+        for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, g[j]);
     if (INSTR) {
         const uint64_t lm = ballot(leader);
-        if (lane == 0) { cnt.sets += TO_LDS ? 0 : popc(lm); cnt.quad_red += 1; cnt.cohesive += 1; }
+        if (lane == 0) { cnt.sets += popc(lm); cnt.quad_red += 1; cnt.cohesive += 1; }
     }
 }
 
@@ -911,8 +903,23 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                     }
                     if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
                 }
-                if (tile_acc) reduce_commit<INSTR, true>(acc, acc_live, tg + k * 9, GS_REDUCE_HYBRID, X, lane, cnt);
-                else if (lane_acc) reduce_commit<INSTR>(acc, acc_live, gp, GS_REDUCE_HYBRID, X, lane, cnt);
+                if (tile_acc) {
+                    // the wave's lane sums reduced at once; the first lane of each 16-lane row
+                    // adds its two (row 0: three) totals to the tile's LDS accumulator
+                    if (ballot(acc_live)) {
+                        float ra, rb, rc;
+                        wave_sum9(acc, ra, rb, rc);
+                        if ((lane & 15) == 0) {
+                            const int row = lane >> 4, j0 = ((row & 1) << 1) | (row >> 1);
+                            atomicAdd(tg + k * 9 + j0, ra);
+                            atomicAdd(tg + k * 9 + j0 + 4, rb);
+                            if (row == 0) atomicAdd(tg + k * 9 + 8, rc);
+                        }
+                        if (INSTR && lane == 0) { cnt.wave_red += 1; cnt.cohesive += 1; }
+                    }
+                } else if (lane_acc) {
+                    reduce_commit<INSTR>(acc, acc_live, gp, GS_REDUCE_HYBRID, X, lane, cnt);
+                }
             }
             if (lane == 0) w.alive[wave] = (int)alive;
             __syncthreads();
