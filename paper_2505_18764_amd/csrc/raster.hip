@@ -35,9 +35,10 @@ constexpr int BATCH = 256;         // splat records staged in LDS at once
 // expanded form a dx^2 + 2b dx dy + c dy^2 cancels terms of size q / (1 - rho^2) (rho the
 // correlation of the footprint) down to q, which in FP32 loses several digits on long thin
 // splats, e.g. those just beyond the near plane whose projected means lie thousands of pixels
-// off-screen; the factored form costs the same instructions. k and det Q / a are formed in FP64
-// from the FP32 conic and stored pre-scaled, a' = -log2(e) a / 2 and d' = -log2(e) det Q / (2a),
-// so that the exponent of alpha = o 2^p is p = a' u^2 + d' dy^2 = -q/2 log2(e), u = dx + k dy.
+// off-screen; the factored form costs the same instructions. det Q is formed in FP64 from the
+// FP32 conic (products exact, one rounding), k and det Q / a in FP32, and they are stored
+// pre-scaled, a' = -log2(e) a / 2 and d' = -log2(e) det Q / (2a), so that the exponent of
+// alpha = o 2^p is p = a' u^2 + d' dy^2 = -q/2 log2(e), u = dx + k dy.
 struct __align__(16) Rec {
     float4 a;
     float4 b;
@@ -182,11 +183,10 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
         if (lane == 0) { items[f] = make_int4(t, 0, wpr, -1); item_w[f] = w; }
         return;
     }
-    int cut[MAX_SEGMENTS + 1];
-    uint32_t cum[MAX_SEGMENTS + 1];
-    cut[0] = 0; cum[0] = 0u;
-#pragma unroll
-    for (int j = 1; j <= MAX_SEGMENTS; ++j) { cut[j] = wpr; cum[j] = w; }
+    __shared__ int cut[MAX_SEGMENTS + 1];            // in LDS: indexed by a runtime j below
+    __shared__ uint32_t cum[MAX_SEGMENTS + 1];
+    if (lane <= MAX_SEGMENTS) { cut[lane] = lane ? wpr : 0; cum[lane] = lane ? w : 0u; }
+    __syncthreads();
     int found = 1;                                   // next cut to find
     uint32_t base = 0u;
     const uint16_t* row = colcnt + (size_t)t * wpr;
@@ -204,13 +204,13 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
             const uint64_t m = ballot(incl >= target && c0 + lane < wpr);
             if (m) {
                 const int l = __builtin_ctzll(m);
-                cut[j] = c0 + l + 1;
-                cum[j] = __shfl(incl, l);
+                if (lane == l) { cut[j] = c0 + l + 1; cum[j] = incl; }
                 found = j + 1;
             }
         }
         base = __shfl(incl, 63);
     }
+    __syncthreads();
     if (lane == 0) {
         cut[k] = wpr; cum[k] = w;
         for (int j = 0; j < k; ++j) {
@@ -285,16 +285,17 @@ __global__ __launch_bounds__(256) void k_raster_setup(
                 float cr = rgb[3 * (size_t)id], cg = rgb[3 * (size_t)id + 1],
                       cb = rgb[3 * (size_t)id + 2];
                 if (saturate) { cr = fminf(cr, 1.f); cg = fminf(cg, 1.f); cb = fminf(cb, 1.f); }
-                // det in FP64: the products of FP32 values are exact, so its sign is exact
-                const double ad = a, bd = b, cd = c;
-                const double det = ad * cd - bd * bd;
+                // det in FP64: the products of FP32 values are exact, so its sign is exact and
+                // its one rounding leaves it accurate to FP32 even when a c and b^2 nearly cancel
+                const double det = (double)a * c - (double)b * b;
                 if (a > 0.f && c > 0.f && det > 0.0 && o >= amin && isfinite(mx) && isfinite(my)) {
+                    const float detf = (float)det;
                     // alpha >= alpha_min  <=>  q <= r2 = 2 ln(o / alpha_min): the ellipse's half
                     // extents are sqrt(r2 Sigma_xx), sqrt(r2 Sigma_yy) with Sigma = conic^-1;
                     // padded so FP32 rounding never puts a passing pixel outside the box.
                     const float r2 = 2.0f * logf(o / amin);
-                    const float hx = (float)sqrt(fmax((double)r2 * cd / det, 0.0)) * 1.001f + 0.01f;
-                    const float hy = (float)sqrt(fmax((double)r2 * ad / det, 0.0)) * 1.001f + 0.01f;
+                    const float hx = sqrtf(fmaxf(r2 * c / detf, 0.f)) * 1.001f + 0.01f;
+                    const float hy = sqrtf(fmaxf(r2 * a / detf, 0.f)) * 1.001f + 0.01f;
                     const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
                     const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), (float)W);
                     const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
@@ -303,10 +304,9 @@ __global__ __launch_bounds__(256) void k_raster_setup(
                         const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
                         const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
                         Rec r;
-                        const double l2e = 1.4426950408889634;
-                        r.a = make_float4(mx, my, -0.5f * LOG2E * a, (float)(bd / ad));
-                        r.b = make_float4((float)(-0.5 * l2e * det / ad), o, cr, cg);
-                        const float pmin = (float)(log2((double)amin) - log2((double)o));
+                        r.a = make_float4(mx, my, -0.5f * LOG2E * a, b / a);
+                        r.b = make_float4(-0.5f * LOG2E * (detf / a), o, cr, cg);
+                        const float pmin = log2f(amin) - log2f(o);
                         r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, __float_as_uint(pmin), 0u);
                         rec[p] = r;
                         const uint32_t tx0 = x0 / TILE, tx1 = (x1 - 1) / TILE;
