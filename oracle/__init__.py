@@ -52,6 +52,7 @@ class OracleConfig:
     beta_abs: float = 0.0
     tau: float = 1e-4
     nthreads: int = 0              # 0: all cores
+    background: tuple = (0.0, 0.0, 0.0)   # C += T_final bg (zero: Eq. 2 as printed)
 
 
 class _OCfg(ctypes.Structure):
@@ -61,7 +62,7 @@ class _OCfg(ctypes.Structure):
                 ("tau", ctypes.c_double), ("fb_format", ctypes.c_int32),
                 ("emulate", ctypes.c_int32), ("fb_round", ctypes.c_int32),
                 ("saturate", ctypes.c_int32), ("prefilter", ctypes.c_int32),
-                ("nthreads", ctypes.c_int32)]
+                ("nthreads", ctypes.c_int32), ("background", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -78,7 +79,7 @@ def lib():
         L.oracle_raster.argtypes = [ctypes.POINTER(_OCfg), ctypes.c_int32, P, P, P, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                    ctypes.c_int32, P, P, P, P, P, P, P]
+                                    ctypes.c_int32, P, P, P, P, P, P, P, P, P]
         L.oracle_round_array.restype = None
         L.oracle_round_array.argtypes = [P, ctypes.c_int64, ctypes.c_int32]
         L.oracle_pixel_trace.restype = ctypes.c_int32
@@ -97,7 +98,8 @@ def _ccfg(cfg: OracleConfig) -> _OCfg:
     nth = cfg.nthreads if cfg.nthreads > 0 else (os.cpu_count() or 1)
     return _OCfg(cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.t_min_bwd, cfg.beta,
                  cfg.beta_abs, cfg.tau, FMT[cfg.fb_format], int(cfg.emulate),
-                 1 if cfg.fb_round == "per_fragment" else 0, int(sat), int(cfg.prefilter), nth)
+                 1 if cfg.fb_round == "per_fragment" else 0, int(sat), int(cfg.prefilter), nth,
+                 (ctypes.c_double * 3)(*[float(v) for v in cfg.background]))
 
 
 def _ptr(a):
@@ -129,11 +131,12 @@ def visible_order(keys: np.ndarray) -> np.ndarray:
 
 
 def raster(means2d, conics, opacities, rgb, order, width, height, crop=None, dL_dimg=None,
-           cfg: OracleConfig | None = None, want_grad=True):
+           cfg: OracleConfig | None = None, want_grad=True, dL_dT=None):
     """Composite the splats listed in ``order`` (front to back) over the crop
     (x0, y0, w, h) of a width x height image; with ``dL_dimg`` ([3, H, W]) also run the
-    backward procedure. Returns img [3,h,w], T [h,w], cov/live/amb [h,w] int32 and, when
-    requested, grad [N, 9] = (dmean x, y, dconic a, b, c, dopacity, drgb r, g, b)."""
+    backward procedure (and with ``dL_dT`` [H, W] the final transmittance's gradient). Returns
+    img [3,h,w], T [h,w], cov/live/amb [h,w] int32 and, when requested, grad [N, 9] = (dmean x,
+    y, dconic a, b, c, dopacity, drgb r, g, b) and grad_bg [3] (w.r.t. the background)."""
     cfg = cfg or OracleConfig()
     m = _c(means2d, np.float64)
     cn = _c(conics, np.float64)
@@ -149,16 +152,20 @@ def raster(means2d, conics, opacities, rgb, order, width, height, crop=None, dL_
     amb = np.zeros((ch, cw), np.int32)
     G = _c(dL_dimg, np.float64) if dL_dimg is not None else None
     grad = np.zeros((n, 9)) if (G is not None and want_grad) else None
+    gT = _c(dL_dT, np.float64) if dL_dT is not None else None
+    gbg = np.zeros(3) if G is not None else None
     c = _ccfg(cfg)
     rc = lib().oracle_raster(ctypes.byref(c), n, _ptr(m), _ptr(cn), _ptr(op), _ptr(cl), _ptr(od),
                              int(od.size), int(width), int(height), int(x0), int(y0), int(cw),
                              int(ch), _ptr(G), _ptr(img), _ptr(T), _ptr(cov), _ptr(live),
-                             _ptr(amb), _ptr(grad))
+                             _ptr(amb), _ptr(grad), _ptr(gT), _ptr(gbg))
     if rc != 0:
         raise ValueError("oracle_raster: invalid arguments")
     out = dict(img=img, T=T, cov=cov, live=live, amb=amb)
     if grad is not None:
         out["grad"] = grad
+    if gbg is not None:
+        out["grad_bg"] = gbg
     return out
 
 

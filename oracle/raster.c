@@ -21,6 +21,11 @@
  *     alpha the gradient to (o, q) is zero; d alpha/d o = exp(-q/2); d alpha/d q = -alpha/2;
  *     dq/da = dx^2, dq/db = 2 dx dy, dq/dc = dy^2, dq/dmu = -2 Q d.
  *
+ * Extension beyond Eq. 2 (zero by default): a background colour bg seen through the final
+ * transmittance, C += T_final bg, which C'_1 = C carries into the backward unchanged; and a
+ * gradient dL/dT_final, which adds -dL/dT_final T_final / (1 - alpha_i) to dL/dalpha_i (the
+ * derivative of T_final = prod (1 - alpha_j)), with dL/dbg = sum over pixels dL/dC T_final.
+ *
  * Mixed-precision emulation (Sec. 3.3): with `emulate` set, the stored per-pixel state (colour
  * and T) is rounded to the framebuffer format either after every fragment store (render-target
  * semantics) or only when the pixel's state is written back at rest; arithmetic stays FP64.
@@ -53,6 +58,7 @@ typedef struct {
     int32_t prefilter; /* 0: every splat at every pixel; 1: skip splats whose exact alpha>=alpha_min
                           ellipse bounding box excludes the pixel centre */
     int32_t nthreads;
+    double background[3]; /* colour behind the last splat: C += T_final bg (0: Eq. 2 as printed) */
 } ocfg_t;
 
 /* ---- format rounding (round to nearest, ties to even, from FP64) ------------------------- */
@@ -154,13 +160,15 @@ int oracle_raster(const ocfg_t* cfg, int32_t n, const double* means2d, const dou
                   const double* opac, const double* rgb, const int32_t* order, int32_t n_order,
                   int32_t W, int32_t H, int32_t x0, int32_t y0, int32_t cw, int32_t ch,
                   const double* dL_dimg, double* out_img, double* out_T, int32_t* out_cov,
-                  int32_t* out_live, int32_t* out_amb, double* grad)
+                  int32_t* out_live, int32_t* out_amb, double* grad, const double* dL_dT,
+                  double* grad_bg)
 {
     if (n < 0 || n_order < 0 || W <= 0 || H <= 0 || cw < 0 || ch < 0) return 1;
     if (x0 < 0 || y0 < 0 || x0 + cw > W || y0 + ch > H) return 1;
     for (int32_t k = 0; k < n_order; ++k)
         if (order[k] < 0 || order[k] >= n) return 1;
     if (grad && !dL_dimg) return 1;
+    if (dL_dT && !dL_dimg) return 1;
     const int fmt = cfg->fb_format;
     const int emu = cfg->emulate;
     const int per_frag = emu && cfg->fb_round == 1;
@@ -214,6 +222,8 @@ int oracle_raster(const ocfg_t* cfg, int32_t n, const double* means2d, const dou
     const double amin = cfg->alpha_min, amax = cfg->alpha_max;
     const double tf = cfg->t_min_fwd, tb = cfg->t_min_bwd;
     const int64_t npix = (int64_t)cw * ch;
+    const double* bg = cfg->background;
+    double* gbg = (double*)calloc((size_t)nth * 3, sizeof(double));
 
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nth)
     for (int64_t pix = 0; pix < npix; ++pix) {
@@ -254,6 +264,10 @@ int oracle_raster(const ocfg_t* cfg, int32_t n, const double* means2d, const dou
                 T = oracle_round_fmt(T, fmt);
             }
         }
+        /* the background shows through the final transmittance; T stays the splats' product */
+        for (int ch3 = 0; ch3 < 3; ++ch3) C[ch3] += T * bg[ch3];
+        if (per_frag)
+            for (int ch3 = 0; ch3 < 3; ++ch3) C[ch3] = oracle_round_fmt(C[ch3], fmt);
         if (emu) {      /* the state written back to the framebuffer */
             for (int ch3 = 0; ch3 < 3; ++ch3) C[ch3] = oracle_round_fmt(C[ch3], fmt);
             T = oracle_round_fmt(T, fmt);
@@ -268,6 +282,10 @@ int oracle_raster(const ocfg_t* cfg, int32_t n, const double* means2d, const dou
             double G[3];
             for (int ch3 = 0; ch3 < 3; ++ch3)
                 G[ch3] = dL_dimg[(int64_t)ch3 * W * H + (int64_t)Y * W + X];
+            /* dL/dT_final: T_final = prod_j (1 - alpha_j), so it adds -dL/dT T_final / (1 - alpha_i)
+               to dL/dalpha_i; and dL/dbg = dL/dC T_final */
+            const double gTT = dL_dT ? dL_dT[(int64_t)Y * W + X] * T : 0.0;
+            for (int ch3 = 0; ch3 < 3; ++ch3) gbg[(size_t)tid * 3 + ch3] += G[ch3] * T;
             double Cp[3] = {C[0], C[1], C[2]}, Tb = 1.0;
             double* gb = gbuf ? gbuf + (size_t)tid * (size_t)nslot * 9 : NULL;
             for (int32_t j = 0; j < ncand; ++j) {
@@ -292,7 +310,7 @@ int oracle_raster(const ocfg_t* cfg, int32_t n, const double* means2d, const dou
                     dL_dc[ch3] = sat[ch3] ? 0.0 : G[ch3] * f.alpha * Tb;               /* Eq. 3 */
                     dL_dalpha += G[ch3] * (cc[ch3] * Tb - Cp[ch3]);                      /* Eq. 7 */
                 }
-                dL_dalpha /= (1.0 - f.alpha);
+                dL_dalpha = (dL_dalpha - gTT) / (1.0 - f.alpha);
                 for (int ch3 = 0; ch3 < 3; ++ch3) Cp[ch3] -= Tb * f.alpha * cc[ch3];  /* Eq. 6 */
                 Tb *= (1.0 - f.alpha);                                                  /* Eq. 5 */
                 if (per_frag) {
@@ -323,6 +341,12 @@ int oracle_raster(const ocfg_t* cfg, int32_t n, const double* means2d, const dou
         if (out_amb) out_amb[pix] = amb;
     }
 
+    if (grad_bg) {
+        grad_bg[0] = grad_bg[1] = grad_bg[2] = 0.0;
+        for (int t = 0; t < nth; ++t)
+            for (int ch3 = 0; ch3 < 3; ++ch3) grad_bg[ch3] += gbg[(size_t)t * 3 + ch3];
+    }
+    free(gbg);
     if (grad) {
         memset(grad, 0, sizeof(double) * (size_t)n * 9);
         for (int32_t k = 0; k < n_order; ++k) {
@@ -374,6 +398,7 @@ int32_t oracle_pixel_trace(const ocfg_t* cfg, int32_t n, const double* means2d,
             T = oracle_round_fmt(T, fmt);
         }
     }
+    for (int c3 = 0; c3 < 3; ++c3) C[c3] += T * cfg->background[c3];
     if (cfg->emulate)
         for (int c3 = 0; c3 < 3; ++c3) C[c3] = oracle_round_fmt(C[c3], fmt);
     for (int c3 = 0; c3 < 3; ++c3) C_final[c3] = C[c3];

@@ -331,3 +331,92 @@ def test_unorm_saturates_colour():
                       cfg=_cfg(prefilter=False, fb_format="unorm16"))
     np.testing.assert_allclose(a["img"][:, 0, 0], [0.5, 0.25, 0.0], atol=1e-15)
     assert a["grad"][0, 6] == 0.0 and a["grad"][0, 7] == pytest.approx(0.5)
+
+
+# ---- background colour and the gradient of the final transmittance --------------------------
+
+def test_background_one_and_two_slabs_closed_form():
+    """With a background bg behind the splats, Eq. 2 becomes C = sum_i T_i alpha_i c_i + T bg with
+    T = prod_i (1 - alpha_i). For one slab: C = o c + (1 - o) bg, dC/do = c - bg, dT/do = -1,
+    dC/dbg = 1 - o. For two: dC/do1 = c1 - o2 c2 - (1 - o2) bg, dC/do2 = (1 - o1) (c2 - bg),
+    dT/do1 = -(1 - o2), dT/do2 = -(1 - o1). L = G.C + gT T (derived by hand)."""
+    bg = np.array([0.15, 0.55, 0.8])
+    G, gT = np.array([0.7, -1.3, 0.25]), -0.45
+    Gimg = np.broadcast_to(G[:, None, None], (3, 1, 1)).copy()
+    GT = np.full((1, 1), gT)
+    cfg = _cfg(prefilter=False, t_min_bwd=0.0, background=tuple(bg))
+    o, c = 0.35, np.array([0.9, 0.1, 0.4])
+    out = oracle.raster(**_slabs([o], [c]), order=np.arange(1), width=1, height=1, dL_dimg=Gimg,
+                        dL_dT=GT, cfg=cfg)
+    np.testing.assert_allclose(out["img"][:, 0, 0], o * c + (1 - o) * bg, rtol=1e-14)
+    np.testing.assert_allclose(out["T"][0, 0], 1 - o, rtol=1e-14)
+    np.testing.assert_allclose(out["grad"][0, 5], G @ (c - bg) - gT, rtol=1e-13)
+    np.testing.assert_allclose(out["grad_bg"], G * (1 - o), rtol=1e-14)
+    o1, o2 = 0.35, 0.6
+    c1, c2 = np.array([0.9, 0.1, 0.4]), np.array([0.2, 0.8, 0.6])
+    out = oracle.raster(**_slabs([o1, o2], [c1, c2]), order=np.arange(2), width=1, height=1,
+                        dL_dimg=Gimg, dL_dT=GT, cfg=cfg)
+    np.testing.assert_allclose(out["grad"][0, 5], G @ (c1 - o2 * c2 - (1 - o2) * bg) - gT * (1 - o2),
+                               rtol=1e-13)
+    np.testing.assert_allclose(out["grad"][1, 5], G @ ((1 - o1) * (c2 - bg)) - gT * (1 - o1),
+                               rtol=1e-13)
+    np.testing.assert_allclose(out["grad"][1, 6:9], G * (1 - o1) * o2, rtol=1e-13)
+    np.testing.assert_allclose(out["grad_bg"], G * (1 - o1) * (1 - o2), rtol=1e-14)
+
+
+def test_background_and_dLdT_finite_differences():
+    """L = sum_p G_p . C_p + gT_p T_p with a background: central differences of the FP64 forward
+    against the backward for every parameter of a few splats and for the background."""
+    g = np.random.default_rng(9)
+    n, W, H = 10, 16, 14
+    means = g.uniform(3, 13, size=(n, 2))
+    conics = []
+    for k in range(n):
+        t = g.uniform(0, np.pi)
+        R = np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]])
+        Q = np.linalg.inv(R @ np.diag(g.uniform(2.0, 4.0, 2) ** 2) @ R.T)
+        conics.append([Q[0, 0], Q[0, 1], Q[1, 1]])
+    s = dict(means2d=means, conics=np.array(conics), opacities=g.uniform(0.2, 0.8, n),
+             rgb=g.uniform(0, 1, (n, 3)))
+    order = np.argsort(g.uniform(size=n)).astype(np.int32)
+    G = g.uniform(-1, 1, size=(3, H, W))
+    GT = g.uniform(-1, 1, size=(H, W))
+    bg = np.array([0.3, 0.6, 0.2])
+
+    def loss(s_, bg_):
+        o = oracle.raster(**s_, order=order, width=W, height=H,
+                          cfg=_cfg(t_min_bwd=0.0, background=tuple(bg_)))
+        return float((G * o["img"]).sum() + (GT * o["T"]).sum()), o
+
+    base = oracle.raster(**s, order=order, width=W, height=H, dL_dimg=G, dL_dT=GT,
+                         cfg=_cfg(t_min_bwd=0.0, background=tuple(bg)))
+    _, b0 = loss(s, bg)
+    h = 1e-6
+    fd, an = [], []
+    # (input array, column, gradient column: mean x, y, conic a, b, c, opacity, rgb r, g, b)
+    for key, col, gcol in (("opacities", None, 5), ("means2d", 0, 0), ("means2d", 1, 1),
+                           ("conics", 0, 2), ("conics", 1, 3), ("conics", 2, 4), ("rgb", 0, 6)):
+        for i in range(n):
+            vals = []
+            for sgn in (1, -1):
+                s2 = {k: v.copy() for k, v in s.items()}
+                if s2[key].ndim == 1:
+                    s2[key][i] += sgn * h
+                else:
+                    s2[key][i, col] += sgn * h
+                l, o = loss(s2, bg)
+                if (o["cov"] != b0["cov"]).any():
+                    break
+                vals.append(l)
+            if len(vals) == 2:
+                fd.append((vals[0] - vals[1]) / (2 * h))
+                an.append(base["grad"][i, gcol])
+    for ch in range(3):
+        bp, bm = bg.copy(), bg.copy()
+        bp[ch] += h
+        bm[ch] -= h
+        fd.append((loss(s, bp)[0] - loss(s, bm)[0]) / (2 * h))
+        an.append(base["grad_bg"][ch])
+    fd, an = np.array(fd), np.array(an)
+    assert len(fd) >= 50
+    assert np.abs(fd - an).max() <= 1e-6 * np.linalg.norm(an), (np.abs(fd - an).max(), np.linalg.norm(an))
