@@ -108,7 +108,9 @@ typedef struct gs_config {
     int32_t reduce_mode;    /* enum gs_reduce_mode */
     int32_t reduce_threshold; /* X of Procedure 2: minimum live lanes for the wave path (8) */
     int32_t flags;          /* enum gs_flags */
-    int32_t reserved[5];
+    float background[3];    /* colour behind the last splat, C += T_final bg; 0 (the default)
+                               is Eq. 2 as printed. Not supported by the tile-based baseline. */
+    int32_t reserved[2];
 } gs_config;
 
 /* Device-side counters (add-only; zero them before the calls you want to count). */
@@ -228,7 +230,8 @@ int gs_raster_setup(const gs_camera* cam, const gs_config* cfg, int32_t n,
  * Forward rasterization (Eq. 2): for every pixel, the splats in sorted_ids[0 .. *n_visible) are
  * composited front to back: alpha = min(alpha_max, o exp(-q/2)), fragments with
  * alpha < alpha_min discarded, C += T alpha c, T *= 1 - alpha (optionally T-culled when
- * cfg->t_min_fwd > 0). The per-pixel state (C, T) is rounded to cfg->fb_format per cfg->fb_round
+ * cfg->t_min_fwd > 0); at the end C += T cfg->background (T stays the splats' product). The
+ * per-pixel state (C, T) is rounded to cfg->fb_format per cfg->fb_round
  * and written to the framebuffer `fb` (gs_framebuffer_size bytes, [H][W][4] in that format).
  * In the unorm formats splat colours saturate to 1 (Sec. 3.3).
  * Inputs [n] by splat id: means2d [n,2], conics [n,3], opacities [n], rgb [n,3];
@@ -253,10 +256,12 @@ int gs_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
  * alpha) (Eq. 7), (C', T) <- (C' - T alpha c, T (1 - alpha)) (Eqs. 5-6), and the chain rule to
  * (mean2d, conic, opacity, rgb); then the reduction of cfg->reduce_mode with threshold X and FP32
  * global atomics.
- * Inputs: as gs_raster_fwd plus fb (the forward's framebuffer, same cfg) and dL_dimage [3,H,W].
+ * Inputs: as gs_raster_fwd plus fb (the forward's framebuffer, same cfg) and dL_dimage [3,H,W];
+ *   dL_dT [H,W] (nullable): the gradient of a loss on the final transmittance T_final =
+ *   prod (1 - alpha_i), which adds -dL_dT T_final / (1 - alpha_i) to dL/dalpha_i.
  * Outputs (overwritten) [n] by splat id: dL_dmeans2d [n,2], dL_dconics [n,3] (w.r.t. a, b, c),
- *   dL_dopacities [n], dL_drgb [n,3]; out_live [H,W] int32 live fragments per pixel (nullable);
- *   stats (nullable).
+ *   dL_dopacities [n], dL_drgb [n,3]; dL_dbackground [3] (nullable) = sum over pixels of
+ *   dL/dC T_final; out_live [H,W] int32 live fragments per pixel (nullable); stats (nullable).
  * Workspace: gs_workspace_size(GS_OP_RASTER_BWD, n, W, H, cfg).
  */
 int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
@@ -264,7 +269,8 @@ int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
                   const float* means2d, const float* conics, const float* opacities,
                   const float* rgb, const void* fb, const float* dL_dimage,
                   float* dL_dmeans2d, float* dL_dconics, float* dL_dopacities, float* dL_drgb,
-                  int32_t* out_live, gs_stats* stats, void* ws, size_t ws_bytes, void* stream);
+                  const float* dL_dT, float* dL_dbackground, int32_t* out_live,
+                  gs_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Backward of the projection (Sec. 2.1.3: "a dedicated subsequent pass"): from the gradients

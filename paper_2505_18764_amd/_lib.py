@@ -36,7 +36,7 @@ class GsConfig(ctypes.Structure):
     _fields_ = [("alpha_min", c_f), ("alpha_max", c_f), ("t_min_fwd", c_f), ("t_min_bwd", c_f),
                 ("eps2d", c_f), ("sh_degree", c_i), ("fb_format", c_i), ("fb_round", c_i),
                 ("reduce_mode", c_i), ("reduce_threshold", c_i), ("flags", c_i),
-                ("reserved", c_i * 5)]
+                ("background", c_f * 3), ("reserved", c_i * 2)]
 
 
 STATS_FIELDS = ["fwd_queued", "fwd_evaluated", "fwd_covered", "bwd_queued", "bwd_evaluated",
@@ -75,7 +75,7 @@ _SIGS = {
                                      c_sz, c_p]),
     "gs_raster_bwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                      c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
-                                     c_p, c_p, c_p, c_sz, c_p]),
+                                     c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_preprocess_bwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                          c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
                                          c_p, c_p, c_p, c_p]),
@@ -186,12 +186,12 @@ def gs_raster_fwd(cam: GsCamera, cfg: GsConfig, n, sorted_ids, n_visible, means2
 
 def gs_raster_bwd(cam: GsCamera, cfg: GsConfig, n, sorted_ids, n_visible, means2d, conics,
                   opacities, rgb, fb, dL_dimage, dL_dmeans2d, dL_dconics, dL_dopacities, dL_drgb,
-                  out_live, stats, ws, ws_bytes, stream):
+                  dL_dT, dL_dbackground, out_live, stats, ws, ws_bytes, stream):
     _check("gs_raster_bwd", lib().gs_raster_bwd(
         ctypes.byref(cam), ctypes.byref(cfg), n, _ptr(sorted_ids), _ptr(n_visible),
         _ptr(means2d), _ptr(conics), _ptr(opacities), _ptr(rgb), _ptr(fb), _ptr(dL_dimage),
-        _ptr(dL_dmeans2d), _ptr(dL_dconics), _ptr(dL_dopacities), _ptr(dL_drgb), _ptr(out_live),
-        _ptr(stats), _ptr(ws), ws_bytes, stream))
+        _ptr(dL_dmeans2d), _ptr(dL_dconics), _ptr(dL_dopacities), _ptr(dL_drgb), _ptr(dL_dT),
+        _ptr(dL_dbackground), _ptr(out_live), _ptr(stats), _ptr(ws), ws_bytes, stream))
 
 
 def gs_preprocess_bwd(cam: GsCamera, cfg: GsConfig, n, means3d, scales, quats, opacities, sh,

@@ -87,6 +87,9 @@ int check_cfg(const gs_config* c) {
         return fail(GS_ERR_INVALID_ARGUMENT, "reduce_threshold %d outside 0..64", c->reduce_threshold);
     if (c->flags & ~(GS_FLAG_STATS | GS_FLAG_REUSE_SETUP))
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", c->flags);
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(c->background[k]))
+            return fail(GS_ERR_INVALID_ARGUMENT, "background must be finite");
     return GS_OK;
 }
 
@@ -113,6 +116,12 @@ int check_ws(void* ws, size_t have, size_t need) {
 int check_align16(const void* p, const char* what) {
     if (((uintptr_t)p) % 16 != 0)
         return fail(GS_ERR_INVALID_ARGUMENT, "%s must be 16-byte aligned", what);
+    return GS_OK;
+}
+
+int check_no_background(const gs_config* c) {
+    if (c->background[0] != 0.f || c->background[1] != 0.f || c->background[2] != 0.f)
+        return fail(GS_ERR_INVALID_ARGUMENT, "the tile-based baseline composites Eq. 2 without a background");
     return GS_OK;
 }
 
@@ -268,7 +277,8 @@ int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const i
                   const int32_t* n_visible, const float* means2d, const float* conics,
                   const float* opacities, const float* rgb, const void* fb, const float* dL_dimage,
                   float* dL_dmeans2d, float* dL_dconics, float* dL_dopacities, float* dL_drgb,
-                  int32_t* out_live, gs_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+                  const float* dL_dT, float* dL_dbackground, int32_t* out_live, gs_stats* stats,
+                  void* ws, size_t ws_bytes, void* stream) {
     if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
@@ -284,7 +294,8 @@ int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const i
     return hip_status(gsr::launch_raster_bwd(*cfg, cam->width, cam->height, n, sorted_ids,
                                              n_visible, means2d, conics, opacities, rgb, fb,
                                              dL_dimage, dL_dmeans2d, dL_dconics, dL_dopacities,
-                                             dL_drgb, out_live, stats, ws, (hipStream_t)stream),
+                                             dL_drgb, dL_dT, dL_dbackground, out_live, stats, ws,
+                                             (hipStream_t)stream),
                       "gs_raster_bwd");
 }
 
@@ -327,6 +338,7 @@ int gs_tile_prepare(const gs_camera* cam, const gs_config* cfg, int32_t n, const
     if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_no_background(cfg));
     GSR_TRY(check_n(n));
     GSR_NEED(n_pairs);
     if (n > 0) {
@@ -347,6 +359,7 @@ int gs_tile_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, co
     if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_no_background(cfg));
     GSR_TRY(check_n(n));
     if (pair_capacity < 0 || pair_capacity > (int64_t)1 << 31)
         return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside 0..2^31");
@@ -371,6 +384,7 @@ int gs_tile_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, co
     if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_no_background(cfg));
     GSR_TRY(check_n(n));
     if (pair_capacity < 0 || pair_capacity > (int64_t)1 << 31)
         return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside 0..2^31");

@@ -32,6 +32,7 @@ struct RasterWs {
     void* rec;         // [n] records in sorted order
     void* rect;        // [n] uint2 tile rectangles
     float* grad;       // [n * GRAD_STRIDE] (backward only)
+    float* bgpart;     // [tiles][4] per-tile dL/dbackground partial sums (backward only)
     unsigned long long* counters;  // [16] planner scratch
     uint32_t* weights; // [tiles] splat count per tile
     int32_t* order;    // [tiles] tiles, heaviest first
@@ -93,7 +94,7 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                              const int32_t* sorted_ids, const int32_t* n_visible,
                              const float* means2d, const float* conics, const float* opac,
                              const float* rgb, const void* fb, const float* dL_dimg,
-                             float* g_means2d, float* g_conics, float* g_opac, float* g_rgb,
+                             float* g_means2d, float* g_conics, float* g_opac, float* g_rgb, const float* dL_dT, float* dL_dbg,
                              int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s);
 
 

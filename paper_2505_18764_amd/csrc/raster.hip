@@ -500,9 +500,9 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x, int ntiles,
     const int4* __restrict__ items, const int32_t* __restrict__ item_order,
     float4* __restrict__ partial,
-    float amin, float amax, float tmin, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
-    float* __restrict__ out_T, int32_t* __restrict__ out_cov,
-    unsigned long long* __restrict__ stats) {
+    float amin, float amax, float tmin, float bg0, float bg1, float bg2, int fb_fmt,
+    void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T,
+    int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
     int tile, c_begin = 0, c_end = wpr, slot = -1;
     if (items) {
@@ -621,7 +621,12 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         if (!valid[s]) continue;
         const int X = wx0 + (s & 1) * 8 + lx, Y = wy0 + (s >> 1) * 8 + ly;
         const size_t i = (size_t)Y * W + X;
-        float4 v = make_float4(C[s][0], C[s][1], C[s][2], T[s]);
+        // the background behind the last splat (a final blend in per-fragment mode)
+        float4 v = make_float4(fmaf(T[s], bg0, C[s][0]), fmaf(T[s], bg1, C[s][1]),
+                               fmaf(T[s], bg2, C[s][2]), T[s]);
+        if constexpr (RFMT >= 0) {
+            v.x = fb_round<RFMT>(v.x); v.y = fb_round<RFMT>(v.y); v.z = fb_round<RFMT>(v.z);
+        }
         fb_store(fb, fb_fmt, i, v);
         if (out_rgb) {
             out_rgb[i] = v.x;
@@ -648,8 +653,9 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
 // (C, T) <- (C + T C_j, T T_j), and writes the framebuffer and the FP32 copies.
 __global__ __launch_bounds__(256) void k_raster_merge(
     int ntiles, int tiles_x, int W, int H, const int32_t* __restrict__ tile_k,
-    const int32_t* __restrict__ tile_first, const float4* __restrict__ partial, int fb_fmt,
-    void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T) {
+    const int32_t* __restrict__ tile_first, const float4* __restrict__ partial, float bg0,
+    float bg1, float bg2, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
+    float* __restrict__ out_T) {
     const int t = blockIdx.x;
     const int k = tile_k[t], f = tile_first[t];
     if (k <= 1 || f < 0 || f + k > ITEMS_PER_TILE * ntiles) return;
@@ -667,7 +673,7 @@ __global__ __launch_bounds__(256) void k_raster_merge(
             T *= v.w;
         }
         const size_t i = (size_t)Y * W + X;
-        float4 v = make_float4(C0, C1, C2, T);
+        float4 v = make_float4(fmaf(T, bg0, C0), fmaf(T, bg1, C1), fmaf(T, bg2, C2), T);
         fb_store(fb, fb_fmt, i, v);                 // v becomes the stored (rounded) state
         if (out_rgb) { out_rgb[i] = v.x; out_rgb[P + i] = v.y; out_rgb[2 * P + i] = v.z; }
         if (out_T) out_T[i] = v.w;
@@ -755,9 +761,9 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     const uint2* __restrict__ rect, const int32_t* __restrict__ order,
     const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x,
     float amin, float amax, float tmin, int fb_fmt, const void* __restrict__ fb,
-    const float* __restrict__ dL_dimg,
-    int mode, int X, float* __restrict__ grad, int32_t* __restrict__ out_live,
-    unsigned long long* __restrict__ stats) {
+    const float* __restrict__ dL_dimg, const float* __restrict__ dL_dT,
+    int mode, int X, float* __restrict__ grad, float* __restrict__ bgpart,
+    int32_t* __restrict__ out_live, unsigned long long* __restrict__ stats) {
     __shared__ Walk w;
     __shared__ float tg[BATCH * 9];     // GS_REDUCE_TILE: per staged splat, the tile's gradient
     int tile = order[blockIdx.x];
@@ -777,9 +783,11 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
 #pragma unroll
         for (int j = 0; j < 9; ++j) tg[tid * 9 + j] = 0.f;
 
-    // Procedure 1's per-pixel state (C', T), initialised to (C, 1) from the framebuffer, and the
-    // read-only dL/dC.
-    float px[4], py[4], Cp[4][3], T[4], G[4][3];
+    // Procedure 1's per-pixel state (C', T), initialised to (C, 1) from the framebuffer, the
+    // read-only dL/dC and, for a loss on the final transmittance, gTT = dL/dT_final T_final
+    // (T_final = prod (1 - alpha_j) contributes -gTT / (1 - alpha_i) to dL/dalpha_i).
+    float px[4], py[4], Cp[4][3], T[4], G[4][3], gTT[4];
+    float gbg[3] = {0.f, 0.f, 0.f};     // this lane's share of dL/dbackground = sum dL/dC T_final
     bool valid[4];
     uint32_t nlive[4];
     uint32_t alive = 0;
@@ -793,11 +801,16 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
         nlive[s] = 0;
         Cp[s][0] = Cp[s][1] = Cp[s][2] = 0.f;
         G[s][0] = G[s][1] = G[s][2] = 0.f;
+        gTT[s] = 0.f;
         if (valid[s]) {
             const size_t i = (size_t)Y * W + X;
             const float4 v = fb_load(fb, fb_fmt, i);
             Cp[s][0] = v.x; Cp[s][1] = v.y; Cp[s][2] = v.z;
             G[s][0] = dL_dimg[i]; G[s][1] = dL_dimg[P + i]; G[s][2] = dL_dimg[2 * P + i];
+            if (dL_dT) gTT[s] = dL_dT[i] * v.w;
+            gbg[0] = fmaf(G[s][0], v.w, gbg[0]);
+            gbg[1] = fmaf(G[s][1], v.w, gbg[1]);
+            gbg[2] = fmaf(G[s][2], v.w, gbg[2]);
         }
         if (ballot(valid[s])) alive |= 1u << s;
     }
@@ -860,9 +873,10 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                         g[6] = G[s][0] * wt;
                         g[7] = G[s][1] * wt;
                         g[8] = G[s][2] * wt;
-                        // Eq. 7: dL/dalpha = dL/dC . (c T - C') / (1 - alpha)
+                        // Eq. 7: dL/dalpha = dL/dC . (c T - C') / (1 - alpha), and the final
+                        // transmittance's share
                         const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) + G[s][1] * (cg * Ti - Cp[s][1]) +
-                                          G[s][2] * (cb * Ti - Cp[s][2])) *
+                                          G[s][2] * (cb * Ti - Cp[s][2]) - gTT[s]) *
                                          __builtin_amdgcn_rcpf(1.f - al);
                         // Eqs. 5, 6: the state update, stored back
                         Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
@@ -928,6 +942,17 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
         if (stop) break;
     }
     if (tile_acc) flush_tile_grad<INSTR>(tg, w, pend, tid, grad, cnt);
+    if (bgpart) {                       // the tile's dL/dbackground, summed in a fixed order
+        __syncthreads();
+        float* red = &tg[0];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float v = wave_sum(gbg[c]);
+            if (lane == 0) red[wave * 3 + c] = v;
+        }
+        __syncthreads();
+        if (tid < 3) bgpart[(size_t)tile * 4 + tid] = red[tid] + red[3 + tid] + red[6 + tid] + red[9 + tid];
+    }
 
     if (INSTR && out_live) {
 #pragma unroll
@@ -988,6 +1013,23 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
     g_rgb[3 * (size_t)id + 2] = v[8];
 }
 
+// dL/dbackground: the per-tile partial sums added in tile order (deterministic).
+__global__ __launch_bounds__(256) void k_bg_reduce(int ntiles, const float* __restrict__ bgpart,
+                                                   float* __restrict__ out) {
+    __shared__ float s[3][256];
+    float a[3] = {0.f, 0.f, 0.f};
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
+        for (int c = 0; c < 3; ++c) a[c] += bgpart[(size_t)t * 4 + c];
+    for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = a[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int c = 0; c < 3; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
 // ---- host side -------------------------------------------------------------------------------
 
 static int tiles_of(int width, int height) {
@@ -1014,7 +1056,7 @@ size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
         b += align_up(nt * wpr * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
              2 * align_up(ITEMS_PER_TILE * nt * 4) + 2 * align_up(nt * 4) +
              align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
-    if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4);
+    if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4) + align_up(nt * 16);
     return b;
 }
 
@@ -1041,7 +1083,11 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
         r.tile_k = (int32_t*)p;     p += align_up(nt * 4);
         r.partial = (float4*)p;     p += align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
     }
-    r.grad = bwd ? (float*)p : nullptr;
+    r.grad = nullptr; r.bgpart = nullptr;
+    if (bwd) {
+        r.grad = (float*)p;   p += align_up((size_t)n * GRAD_STRIDE * 4);
+        r.bgpart = (float*)p; p += align_up(nt * 16);
+    }
     return r;
 }
 
@@ -1087,8 +1133,8 @@ hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int 
 
 using FwdKernel = void (*)(int, const int32_t*, const Rec*, const uint2*, const int32_t*,
                           const uint32_t*, int, int, int, int, int, const int4*, const int32_t*,
-                          float4*, float, float, float, int, void*, float*, float*, int32_t*,
-                          unsigned long long*);
+                          float4*, float, float, float, float, float, float, int, void*, float*,
+                          float*, int32_t*, unsigned long long*);
 
 template <bool TC, bool IN>
 static FwdKernel fwd_by_fmt(int rfmt) {
@@ -1128,14 +1174,16 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                        (const uint32_t*)r.bits, r.wpr, width, height, tiles_x, ntiles,
                        split ? (const int4*)r.items : nullptr,
                        split ? (const int32_t*)r.item_order : nullptr, split ? r.partial : nullptr,
-                       cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.fb_format, fb, out_rgb, out_T,
+                       cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.background[0],
+                       cfg.background[1], cfg.background[2], cfg.fb_format, fb, out_rgb, out_T,
                        out_cov,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !split) return e;
     hipLaunchKernelGGL(k_raster_merge, dim3(ntiles), dim3(256), 0, s, ntiles, tiles_x, width, height,
                        (const int32_t*)r.tile_k, (const int32_t*)r.tile_first,
-                       (const float4*)r.partial, cfg.fb_format, fb, out_rgb, out_T);
+                       (const float4*)r.partial, cfg.background[0], cfg.background[1],
+                       cfg.background[2], cfg.fb_format, fb, out_rgb, out_T);
     return hipGetLastError();
 }
 
@@ -1143,7 +1191,7 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                              const int32_t* sorted_ids, const int32_t* n_visible,
                              const float* means2d, const float* conics, const float* opac,
                              const float* rgb, const void* fb, const float* dL_dimg,
-                             float* g_means2d, float* g_conics, float* g_opac, float* g_rgb,
+                             float* g_means2d, float* g_conics, float* g_opac, float* g_rgb, const float* dL_dT, float* dL_dbg,
                              int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s) {
     const RasterWs r = carve_raster_ws(ws, n, width, height, true);
     const int sat = (int)saturating(cfg.fb_format);
@@ -1161,8 +1209,8 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_live;
     void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
-              int, int, int, float, float, float, int, const void*, const float*, int, int, float*,
-              int32_t*, unsigned long long*) = nullptr;
+              int, int, int, float, float, float, int, const void*, const float*, const float*, int,
+              int, float*, float*, int32_t*, unsigned long long*) = nullptr;
 #define GSR_BWD_PICK(IN)                                             \
     switch (rfmt) {                                                  \
     case FB_F32: k = k_raster_bwd<FB_F32, IN>; break;                \
@@ -1178,11 +1226,18 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                        (const uint2*)r.rect, (const int32_t*)r.order, (const uint32_t*)r.bits,
                        r.wpr, width, height, tiles_x,
                        cfg.alpha_min, cfg.alpha_max, cfg.t_min_bwd, cfg.fb_format, fb, dL_dimg,
-                       cfg.reduce_mode,
-                       cfg.reduce_threshold, r.grad, out_live,
+                       dL_dT, cfg.reduce_mode, cfg.reduce_threshold, r.grad,
+                       dL_dbg ? r.bgpart : nullptr, out_live,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n == 0) return e;
+    if (e != hipSuccess) return e;
+    if (dL_dbg) {
+        hipLaunchKernelGGL(k_bg_reduce, dim3(1), dim3(256), 0, s, nblocks, (const float*)r.bgpart,
+                           dL_dbg);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
                        n_visible, r.grad, rgb, sat, g_means2d, g_conics, g_opac, g_rgb);
     return hipGetLastError();

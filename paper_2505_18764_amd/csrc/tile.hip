@@ -19,11 +19,13 @@ constexpr int BT_THREADS = 256; // one pixel per thread
 __device__ __forceinline__ bool splat_box(float mx, float my, float a, float b, float c, float o,
                                           float amin, int W, int H, uint32_t& x0, uint32_t& x1,
                                           uint32_t& y0, uint32_t& y1) {
-    const float det = a * c - b * b;
-    if (!(a > 0.f && c > 0.f && det > 0.f && o >= amin && isfinite(mx) && isfinite(my))) return false;
+    // det in FP64: the products of FP32 values are exact (thin splats cancel a c against b^2)
+    const double det = (double)a * c - (double)b * b;
+    if (!(a > 0.f && c > 0.f && det > 0.0 && o >= amin && isfinite(mx) && isfinite(my))) return false;
+    const float detf = (float)det;
     const float r2 = 2.0f * logf(o / amin);
-    const float hx = sqrtf(fmaxf(r2 * c / det, 0.f)) * 1.001f + 0.01f;
-    const float hy = sqrtf(fmaxf(r2 * a / det, 0.f)) * 1.001f + 0.01f;
+    const float hx = sqrtf(fmaxf(r2 * c / detf, 0.f)) * 1.001f + 0.01f;
+    const float hy = sqrtf(fmaxf(r2 * a / detf, 0.f)) * 1.001f + 0.01f;
     const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
     const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), (float)W);
     const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
@@ -98,8 +100,11 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict_
     }
 }
 
+// A staged splat. The conic is kept in its LDL^T factors, q = a (dx + k dy)^2 + d dy^2 with
+// k = b / a and d = det / a: two non-negative terms, where the expanded a dx^2 + 2b dx dy + c dy^2
+// cancels large terms on long thin splats in FP32.
 struct TRec {
-    float mx, my, a, b, c, o, r, g, bl;
+    float mx, my, a, k, d, o, r, g, bl;
     int id;
 };
 
@@ -110,9 +115,11 @@ __device__ __forceinline__ void load_trec(TRec& t, int id, const float* __restri
     t.id = id;
     t.mx = means2d[2 * (size_t)id];
     t.my = means2d[2 * (size_t)id + 1];
-    t.a = conics[3 * (size_t)id];
-    t.b = conics[3 * (size_t)id + 1];
-    t.c = conics[3 * (size_t)id + 2];
+    const float a = conics[3 * (size_t)id], b = conics[3 * (size_t)id + 1],
+                c = conics[3 * (size_t)id + 2];
+    t.a = a;
+    t.k = b / a;
+    t.d = (float)((double)a * c - (double)b * b) / a;
     t.o = opac[id];
     t.r = rgb[3 * (size_t)id];
     t.g = rgb[3 * (size_t)id + 1];
@@ -146,7 +153,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_tile_fwd(
         for (uint32_t k = 0; k < m && !done; ++k) {
             const TRec& s = s_rec[k];
             const float dx = px - s.mx, dy = py - s.my;
-            const float q = s.a * dx * dx + 2.f * s.b * dx * dy + s.c * dy * dy;
+            const float u = fmaf(s.k, dy, dx);
+            const float q = fmaf(s.a * u, u, s.d * dy * dy);
             const float al = fminf(amax, s.o * __expf(-0.5f * q));
             if (al < amin) continue;
             const float w = al * T;
@@ -208,7 +216,9 @@ __global__ __launch_bounds__(BT_THREADS) void k_tile_bwd(
             if (b0 + k - rg.x >= last) continue;
             const TRec& s = s_rec[k];
             const float dx = px - s.mx, dy = py - s.my;
-            const float q = s.a * dx * dx + 2.f * s.b * dx * dy + s.c * dy * dy;
+            const float u = fmaf(s.k, dy, dx);
+            const float au = s.a * u;
+            const float q = fmaf(au, u, s.d * dy * dy);
             const float e = __expf(-0.5f * q);
             const float araw = s.o * e;
             const float al = fminf(amax, araw);
@@ -227,8 +237,9 @@ __global__ __launch_bounds__(BT_THREADS) void k_tile_bwd(
             if (araw < amax) {
                 const float gq = -0.5f * ga * araw;
                 atomic_add_f32(&g_o[id], ga * e);
-                atomic_add_f32(&g_m[2 * (size_t)id], -2.f * gq * (s.a * dx + s.b * dy));
-                atomic_add_f32(&g_m[2 * (size_t)id + 1], -2.f * gq * (s.b * dx + s.c * dy));
+                // dq/dmu = -2 Q d with Q d = (a u, k a u + d dy) in the factored form
+                atomic_add_f32(&g_m[2 * (size_t)id], -2.f * gq * au);
+                atomic_add_f32(&g_m[2 * (size_t)id + 1], -2.f * gq * fmaf(s.k, au, s.d * dy));
                 atomic_add_f32(&g_c[3 * (size_t)id], gq * dx * dx);
                 atomic_add_f32(&g_c[3 * (size_t)id + 1], 2.f * gq * dx * dy);
                 atomic_add_f32(&g_c[3 * (size_t)id + 2], gq * dy * dy);

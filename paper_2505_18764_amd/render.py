@@ -27,7 +27,7 @@ class RasterConfig:
     1/255, backward T-cull 1e-4, no forward T-cull, hybrid reduction with X = 8, FP32 state."""
     fb_format: str = "f32"            # f32 | f16 | unorm16 | bf16 | unorm8
     fb_round: str = "at_rest"         # at_rest | per_fragment
-    reduce_mode: str = "hybrid"       # naive | quad | wave | hybrid | hybrid_lane
+    reduce_mode: str = "hybrid"       # naive | quad | wave | hybrid | hybrid_lane | tile
     reduce_threshold: int = 8
     t_min_fwd: float = 0.0
     t_min_bwd: float = _f32(1e-4)
@@ -36,6 +36,7 @@ class RasterConfig:
     eps2d: float = _f32(0.3)
     sh_degree: int = 3
     stats: bool = False
+    background: tuple = (0.0, 0.0, 0.0)   # C += T_final background (zero: Eq. 2 as printed)
 
     def c(self) -> L.GsConfig:
         c = L.GsConfig()
@@ -50,6 +51,8 @@ class RasterConfig:
         c.reduce_mode = L.REDUCE_MODES[self.reduce_mode]
         c.reduce_threshold = self.reduce_threshold
         c.flags = 1 if self.stats else 0
+        for k in range(3):
+            c.background[k] = float(self.background[k])
         return c
 
 
@@ -235,8 +238,9 @@ def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, imag
 
 
 def raster_backward(p: Projected, fb, dL_dimage, cfg: RasterConfig, ws: Workspace, live=False,
-                    stats=None, out=None, reuse_setup=False):
-    """gs_raster_bwd: gradients w.r.t. (means2d, conics, opacities, rgb) by splat id.
+                    stats=None, out=None, reuse_setup=False, dL_dT=None):
+    """gs_raster_bwd: gradients w.r.t. (means2d, conics, opacities, rgb) by splat id and w.r.t.
+    the background ('background' [3]); dL_dT [H, W] is an optional gradient of the final T.
     reuse_setup: the workspace holds raster_setup's output for exactly these inputs."""
     dev = p.means2d.device
     W, H, n = p.width, p.height, p.n
@@ -246,13 +250,16 @@ def raster_backward(p: Projected, fb, dL_dimage, cfg: RasterConfig, ws: Workspac
     if out is None:
         out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
                    opacities=torch.empty(n, device=dev), rgb=torch.empty(n, 3, device=dev))
+    if "background" not in out:
+        out["background"] = torch.empty(3, device=dev)
     lv = torch.empty(H, W, dtype=torch.int32, device=dev) if live else None
     if stats is not None:
         cc.flags |= 1
     b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc))
     L.gs_raster_bwd(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, fb,
                     _c32(dL_dimage), out["means2d"], out["conics"], out["opacities"], out["rgb"],
-                    lv, stats, b, nb, _stream(dev))
+                    None if dL_dT is None else _c32(dL_dT), out["background"], lv, stats, b, nb,
+                    _stream(dev))
     out["live"] = lv
     return out
 
@@ -278,23 +285,25 @@ def project_backward(means3d, scales, quats, opacities, sh, cam, cfg: RasterConf
 
 class GaussianRasterizeFn(torch.autograd.Function):
     """image, T = f(means3d, scales, quats, opacities, sh): projection, depth sort, ordered
-    compositing; the backward runs Procedures 1-2 and the projection's backward. Activations
-    (exp of log-scales, sigmoid of logits) stay in torch, outside this function. The returned T
-    carries no gradient (the procedure takes only dL/dC)."""
+    compositing (over cfg.background); the backward runs Procedures 1-2 and the projection's
+    backward. Activations (exp of log-scales, sigmoid of logits) stay in torch, outside this
+    function. A loss on the final T (e.g. an alpha mask) reaches the splats through dL/dT."""
 
     @staticmethod
     def forward(ctx, means3d, scales, quats, opacities, sh, cam, cfg, ws):
+        ctx.set_materialize_grads(False)
         p = project(means3d, scales, quats, opacities, sh, cam, cfg, ws)
         out = raster_forward(p, cfg, ws)
         ctx.cam, ctx.cfg, ctx.ws, ctx.proj = cam, cfg, ws, p
         ctx.save_for_backward(means3d, scales, quats, opacities, sh, out["fb"])
-        ctx.mark_non_differentiable(out["T"])
         return out["image"], out["T"]
 
     @staticmethod
     def backward(ctx, d_image, d_T):
         means3d, scales, quats, opacities, sh, fb = ctx.saved_tensors
-        g2 = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws)
+        if d_image is None:
+            d_image = torch.zeros(3, ctx.proj.height, ctx.proj.width, device=fb.device)
+        g2 = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws, dL_dT=d_T)
         g3 = project_backward(means3d, scales, quats, opacities, sh, ctx.cam, ctx.cfg, g2)
         return g3["means3d"], g3["scales"], g3["quats"], g3["opacities"], g3["sh"], None, None, None
 
@@ -304,17 +313,19 @@ class Raster2DFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, means2d, conics, opacities, rgb, depth, width, height, cfg, ws):
+        ctx.set_materialize_grads(False)
         p = prepare_2d(means2d, conics, opacities, rgb, depth, width, height, cfg, ws)
         out = raster_forward(p, cfg, ws)
         ctx.cfg, ctx.ws, ctx.proj = cfg, ws, p
         ctx.save_for_backward(out["fb"])
-        ctx.mark_non_differentiable(out["T"])
         return out["image"], out["T"]
 
     @staticmethod
     def backward(ctx, d_image, d_T):
         (fb,) = ctx.saved_tensors
-        g = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws)
+        if d_image is None:
+            d_image = torch.zeros(3, ctx.proj.height, ctx.proj.width, device=fb.device)
+        g = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws, dL_dT=d_T)
         return g["means2d"], g["conics"], g["opacities"], g["rgb"], None, None, None, None, None
 
 
@@ -363,6 +374,8 @@ def tile_backward(p: Projected, fwd: dict, dL_dimage, cfg: RasterConfig, ws: Wor
     if out is None:
         out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
                    opacities=torch.empty(n, device=dev), rgb=torch.empty(n, 3, device=dev))
+    if "background" not in out:
+        out["background"] = torch.empty(3, device=dev)
     b = ws.get(L.gs_tile_workspace_size(n, fwd["capacity"], W, H), keep=True)
     L.gs_tile_raster_bwd(cm, cc, n, p.means2d, p.conics, p.opacities, p.rgb, _c32(dL_dimage),
                          fwd["T"], fwd["n_contrib"], fwd["capacity"], out["means2d"],

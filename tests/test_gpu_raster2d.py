@@ -274,3 +274,58 @@ def test_prepare_2d_order_matches_oracle():
     np.testing.assert_array_equal(ids[:nv], ref[vis[ref]])
     assert sorted(ids) == list(range(5000))
     del c
+
+
+@pytest.mark.parametrize("mode", ["hybrid", "tile"])
+def test_background_and_transmittance_gradient(mode):
+    """A background behind the splats (C += T_final bg) and a loss on the final transmittance
+    (dL/dT_final), against the oracle: image and T from the depth-split forward and from the
+    one-pass forward, splat gradients, and dL/dbackground."""
+    W, H = 200, 136
+    s = synth.splats2d(n=4000, width=W, height=H, seed=33)
+    g = np.random.default_rng(34)
+    G = g.uniform(-1, 1, size=(3, H, W)).astype(np.float32)
+    GT = g.uniform(-1, 1, size=(H, W)).astype(np.float32)
+    bg = (0.2, 0.45, 0.9)
+    cfg = R.RasterConfig(reduce_mode=mode, background=bg)
+    ws = R.Workspace()
+    p = R.prepare_2d(t(s.means2d), t(s.conics), t(s.opacities), t(s.rgb), t(s.depth), W, H, cfg, ws)
+    R.raster_setup(p, cfg, ws)
+    f = R.raster_forward(p, cfg, ws, reuse_setup=True)
+    b = R.raster_backward(p, f["fb"], t(G), cfg, ws, live=True, reuse_setup=True, dL_dT=t(GT))
+    f1 = R.raster_forward(p, cfg, ws, coverage=True, reuse_setup=True)
+    torch.cuda.synchronize()
+    ref = oracle.raster(s.means2d, s.conics, s.opacities, s.rgb, oracle.depth_order(s.depth), W, H,
+                        dL_dimg=G, dL_dT=GT, cfg=oracle.OracleConfig(background=bg, **BAND))
+    ok = ref["amb"] == 0
+    for ff in (f, f1):
+        assert np.abs(ff["image"].cpu().numpy() - ref["img"])[:, ok].max() <= 1e-5
+        assert np.abs(ff["T"].cpu().numpy() - ref["T"])[ok].max() <= 1e-5
+    e = group_errors(grads9(b), ref["grad"])
+    gbg = b["background"].cpu().numpy()
+    print(mode, e, "dL/dbg", gbg, ref["grad_bg"])
+    assert e["all"] <= 1e-4, e
+    np.testing.assert_allclose(gbg, ref["grad_bg"], rtol=1e-5)
+    # zero background and no dL/dT: the plain path, unchanged
+    assert np.abs(ref["img"] - oracle.raster(s.means2d, s.conics, s.opacities, s.rgb,
+                                             oracle.depth_order(s.depth), W, H)["img"]).max() > 1e-3
+
+
+def test_autograd_loss_on_transmittance():
+    """Raster2DFn: a loss on T (an alpha mask) reaches the splats through dL/dT."""
+    W, H = 96, 72
+    s = synth.splats2d(n=800, width=W, height=H, seed=35)
+    g = np.random.default_rng(36)
+    G = g.uniform(-1, 1, size=(3, H, W)).astype(np.float32)
+    GT = g.uniform(-1, 1, size=(H, W)).astype(np.float32)
+    leaves = [t(a).requires_grad_(True) for a in (s.means2d, s.conics, s.opacities, s.rgb)]
+    img, T = R.rasterize_2d(*leaves, t(s.depth), W, H, R.RasterConfig(reduce_mode="tile"))
+    ((img * t(G)).sum() + (T * t(GT)).sum()).backward()
+    torch.cuda.synchronize()
+    ref = oracle.raster(s.means2d, s.conics, s.opacities, s.rgb, oracle.depth_order(s.depth), W, H,
+                        dL_dimg=G, dL_dT=GT, cfg=oracle.OracleConfig(**BAND))
+    got = np.concatenate([leaves[0].grad.cpu().numpy(), leaves[1].grad.cpu().numpy(),
+                          leaves[2].grad.cpu().numpy()[:, None], leaves[3].grad.cpu().numpy()], 1)
+    e = group_errors(got, ref["grad"])
+    print(e)
+    assert e["all"] <= 1e-4, e
