@@ -45,6 +45,8 @@ def _parse():
                     help="requests of the serving run (0: skip); 100 more are warmup")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-format-errors", action="store_true",
+                    help="skip the low-precision gradient error table")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="write profiles/traffic.json from DIR/{fetch,write,cfetch,cwrite} "
                          "rocprofv3 databases (no GPU work)")
@@ -67,6 +69,22 @@ def _traffic(kernels):
             return None
         tot += e["bytes_per_launch"]
     return tot
+
+
+def format_error_table(g, g_ref):
+    """The paper's mixed-precision error measure (Sec. 4, Table 3): RMSE of all gradient
+    elements against the FP32 path, and the mean relative error |g - g_ref| / |g_ref| over the
+    elements whose reference magnitude lies in [10, inf), [0.1, 10) and [1e-3, 0.1)."""
+    g = np.asarray(g, np.float64).reshape(-1)
+    r = np.asarray(g_ref, np.float64).reshape(-1)
+    out = {"rmse": float(np.sqrt(np.mean((g - r) ** 2))) if r.size else 0.0}
+    a = np.abs(r)
+    for name, lo, hi in (("mre_10_inf", 10.0, np.inf), ("mre_0.1_10", 0.1, 10.0),
+                         ("mre_1e-3_0.1", 1e-3, 0.1)):
+        m = (a >= lo) & (a < hi)
+        out[name] = float(np.mean(np.abs(g[m] - r[m]) / a[m])) if m.any() else None
+        out["n_" + name[4:]] = int(m.sum())
+    return out
 
 
 # the launches of the timed raster stages (paper mode, FP16 at rest, no counters)
@@ -245,6 +263,10 @@ def main():
         extra["fwd_tcull_ms_per_view"] = r["ms_per_view"]
         extra["fwd_tcull_stages_ms"] = r["stages_ms"]
 
+    format_errors = None
+    if not args.no_format_errors:
+        format_errors = format_error_run(inp, cam, Gd, R, dev)
+
     serving = None
     if args.serve_requests > 0:
         serving = serving_run(args.serve_requests, dev)
@@ -286,11 +308,38 @@ def main():
         "roofline_kernels": roof,
         "workspace_bytes": head["ws_bytes"],
         "tile_baseline": tile,
+        "format_errors": format_errors,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     line.update(extra)
     print(json.dumps(line), flush=True)
+
+
+def format_error_run(inp, cam, Gd, R, dev):
+    """Gradients of the 3D parameters (means, scales, quaternions, opacities, SH) with each
+    low-precision framebuffer against the FP32 framebuffer on the benchmark view, in the two
+    rounding modes (state rounded at rest; rounded after every fragment as a render target)."""
+    import torch
+
+    def grads(fmt, rnd):
+        cfg = R.RasterConfig(fb_format=fmt, fb_round=rnd, reduce_mode="tile")
+        ws = R.Workspace(dev)
+        p = R.project(*inp, cam, cfg, ws)
+        f = R.raster_forward(p, cfg, ws)
+        g2 = R.raster_backward(p, f["fb"], Gd, cfg, ws)
+        g3 = R.project_backward(*inp, cam, cfg, g2)
+        torch.cuda.synchronize()
+        return np.concatenate([g3[k].detach().cpu().numpy().reshape(-1)
+                               for k in ("means3d", "scales", "quats", "opacities", "sh")])
+
+    ref = grads("f32", "at_rest")
+    out = {"reference": "FP32 framebuffer", "parameters": "means, scales, quats, opacities, SH"}
+    for rnd in ("at_rest", "per_fragment"):
+        for fmt in ("f16", "unorm16", "bf16", "unorm8"):
+            out[f"{fmt}/{rnd}"] = {k: (round(v, 5) if isinstance(v, float) else v)
+                                   for k, v in format_error_table(grads(fmt, rnd), ref).items()}
+    return out
 
 
 def serving_run(n_requests, dev, warmup=100, rate=200.0):
