@@ -41,6 +41,8 @@ def _parse():
     ap.add_argument("--cpu-blocks", type=int, default=96)
     ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-based baseline")
+    ap.add_argument("--no-views", action="store_true",
+                    help="skip the several-views-per-call measurement (fitting workload)")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests of the serving run (0: skip); 100 more are warmup")
     ap.add_argument("--copy-probe", action="store_true",
@@ -267,6 +269,8 @@ def main():
     if not args.no_format_errors:
         format_errors = format_error_run(inp, cam, Gd, R, dev)
 
+    views = None if args.no_views else views_run(dev)
+
     serving = None
     if args.serve_requests > 0:
         serving = serving_run(args.serve_requests, dev)
@@ -309,6 +313,7 @@ def main():
         "workspace_bytes": head["ws_bytes"],
         "tile_baseline": tile,
         "format_errors": format_errors,
+        "views_per_call": views,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -339,6 +344,75 @@ def format_error_run(inp, cam, Gd, R, dev):
         for fmt in ("f16", "unorm16", "bf16", "unorm8"):
             out[f"{fmt}/{rnd}"] = {k: (round(v, 5) if isinstance(v, float) else v)
                                    for k, v in format_error_table(grads(fmt, rnd), ref).items()}
+    return out
+
+
+def views_run(dev, steps=10, warmup=2):
+    """The fitting workload's step over all its cameras (500k Gaussians, 8 ring cameras,
+    1280x720, FP16 framebuffer, dL/dC ~ U[-1, 1] per view): projection, sort, raster setup,
+    forward, backward and projection backward with the 3D gradients summed over the views, run as
+    8 one-view calls (the sums added by torch) and as calls of 2, 4 and 8 views (the library sums).
+    Returns ms per view of each."""
+    import torch
+    import synth
+    from paper_2505_18764_amd import render as R
+    c = synth.CFG4
+    W, H = c["width"], c["height"]
+    sc = synth.scene3d(c["n_train"], seed=c["seed_train"])
+    cams = [synth.camera_ring(k, c["cameras"], width=W, height=H, fx=c["fx"])
+            for k in range(c["cameras"])]
+    V = len(cams)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    inp = [t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh)]
+    Gd = t(np.stack([synth.image_grad(W, H, 300 + v) for v in range(V)]))
+    cfg = R.RasterConfig(fb_format="f16", reduce_mode="tile")
+    keys3 = ("means3d", "scales", "quats", "opacities", "sh")
+
+    def make(vb):
+        ws = R.Workspace(dev)
+        cs = cams[:vb] if vb > 1 else cams[0]
+        q = R.project(*inp, cs, cfg, ws)
+        R.raster_setup(q, cfg, ws)
+        f = R.raster_forward(q, cfg, ws, reuse_setup=True)
+        g2 = R.raster_backward(q, f["fb"], Gd[:vb] if vb > 1 else Gd[0], cfg, ws, reuse_setup=True)
+        g3 = R.project_backward(*inp, cs, cfg, g2)
+        return ws, f, g2, g3
+
+    def run(vb):
+        ws, f, g2, g3 = make(vb)
+        acc = {k: torch.zeros_like(x) for k, x in zip(keys3, inp)}
+
+        def step():
+            for a in acc.values():
+                a.zero_()
+            for v0 in range(0, V, vb):
+                cs = cams[v0:v0 + vb] if vb > 1 else cams[v0]
+                Gv = Gd[v0:v0 + vb] if vb > 1 else Gd[v0]
+                q = R.project(*inp, cs, cfg, ws)
+                R.raster_setup(q, cfg, ws)
+                R.raster_forward(q, cfg, ws, fb=f["fb"], image=f["image"], T=f["T"],
+                                 reuse_setup=True)
+                R.raster_backward(q, f["fb"], Gv, cfg, ws, out=g2, reuse_setup=True)
+                R.project_backward(*inp, cs, cfg, g2, out=g3)
+                for k in keys3:
+                    acc[k].add_(g3[k])
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps / V
+
+    out = {"workload": f"{c['n_train']} clustered 3D Gaussians, {V} ring cameras, {W}x{H}, "
+                       "FP16 framebuffer, tile reduction; 3D gradients summed over the views",
+           "ms_per_view": {}}
+    for vb in (1, 2, 4, 8):
+        out["ms_per_view"][f"{vb}_views_per_call"] = round(run(vb), 4)
     return out
 
 

@@ -23,6 +23,20 @@
  *     at zero.
  *   - Width and height are 1 .. 16384; n is 0 .. 2^28.
  *   - Nothing here is thread-safe across calls that share a workspace.
+ *
+ * Several views per launch (cfg->n_views = V, 2 .. GS_MAX_VIEWS; 0 and 1 mean one view): the
+ * views are cameras of one scene with the same image size, processed by the same kernels with the
+ * view as the grid's second dimension. Every per-view array is then the concatenation of the V
+ * views' arrays: [V][n][..] by splat id (means2d, conics, rgb, depth, keys, ids and the 2D
+ * gradients), [V] for n_visible, [V][3][H][W] / [V][H][W] images, V framebuffers back to back.
+ * Per-Gaussian inputs that do not depend on the view (the 3D parameters, opacities) stay [n].
+ * Gradients w.r.t. quantities shared by the views are summed over them: gs_preprocess_bwd writes
+ * the sum of the V views' 3D gradients and gs_raster_bwd the sum of their dL/dbackground. The
+ * workspace is cut into V equal slabs of floor(ws_bytes / V / 256) * 256 bytes, one per view; each
+ * must hold the op's one-view size (gs_workspace_size returns V times that size, rounded up to
+ * 256 bytes). Calls that pass state through the workspace (gs_raster_setup -> gs_raster_fwd ->
+ * gs_raster_bwd with GS_FLAG_REUSE_SETUP) must pass the same ws_bytes. Only the ordered path
+ * batches views: gs_prepare_2d and the tile-based baseline reject n_views > 1.
  */
 #ifndef GSR_H
 #define GSR_H
@@ -35,6 +49,7 @@ extern "C" {
 #endif
 
 #define GSR_ABI_VERSION 1
+#define GS_MAX_VIEWS 16
 
 enum gs_status {
     GS_OK = 0,
@@ -110,7 +125,8 @@ typedef struct gs_config {
     int32_t flags;          /* enum gs_flags */
     float background[3];    /* colour behind the last splat, C += T_final bg; 0 (the default)
                                is Eq. 2 as printed. Not supported by the tile-based baseline. */
-    int32_t reserved[2];
+    int32_t n_views;        /* views per call (0 or 1: one; up to GS_MAX_VIEWS), see above */
+    int32_t reserved[1];
 } gs_config;
 
 /* Device-side counters (add-only; zero them before the calls you want to count). */
@@ -149,7 +165,8 @@ int32_t gs_version(void);
  * sh_degree 3, F32 framebuffer rounded at rest, HYBRID reduction with X = 8. */
 void gs_config_default(gs_config* cfg);
 
-/* Bytes of scratch the op needs for n splats at width x height. Pure host function of its
+/* Bytes of scratch the op needs for n splats at width x height (times cfg->n_views, each view's
+ * part rounded up to 256 bytes; cfg may be NULL for one view). Pure host function of its
  * arguments (no HIP call); 0 for invalid arguments. Every buffer in the library has a size that
  * is a closed form of (n, width, height, format): this is what a server admits requests by. */
 size_t gs_workspace_size(int32_t op, int32_t n, int32_t width, int32_t height,
@@ -177,6 +194,8 @@ size_t gs_framebuffer_size(int32_t width, int32_t height, int32_t fb_format);
  *   order as (0xFFFFFFFF, id); n_visible [1] (device int32) is the number of visible splats.
  *   The compaction is deterministic (a prefix sum, no atomics).
  * Workspace: gs_workspace_size(GS_OP_PREPROCESS, n, ...).
+ * With cfg->n_views = V, cam points to V cameras (equal width and height) and the outputs are
+ * [V][..] as described at the top.
  */
 int gs_preprocess(const gs_camera* cam, const gs_config* cfg, int32_t n,
                   const float* means3d, const float* scales, const float* quats,
@@ -207,6 +226,15 @@ int gs_prepare_2d(const gs_camera* cam, const gs_config* cfg, int32_t n,
  */
 int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible,
             void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gs_sort for n_views views in one launch per step: keys [n_views][n], ids [n_views][n],
+ * n_visible [n_views]; each view's first n_visible[v] pairs are sorted as gs_sort does. The
+ * workspace is cut into n_views slabs as described at the top (each needs
+ * gs_workspace_size(GS_OP_SORT, n, ...) bytes with one view). n_views is 1 .. GS_MAX_VIEWS.
+ */
+int gs_sort_views(int32_t n_views, int32_t n, uint32_t* keys, int32_t* ids,
+                  const int32_t* n_visible, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Raster setup, shared by the forward and the backward walk: per sorted position, the splat's
@@ -280,6 +308,8 @@ int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
  * Outputs (overwritten): dL_dmeans3d [n,3], dL_dscales [n,3], dL_dquats [n,4],
  *   dL_dopacities [n], dL_dsh [n,(sh_degree+1)^2,3]. sh and dL_dsh must be 16-byte aligned.
  *   Workspace: none.
+ * With cfg->n_views = V: cam points to V cameras, the 2D gradients are [V][n][..], and each
+ *   output is the sum over the views (in view order, accumulated in registers and written once).
  */
 int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
                       const float* means3d, const float* scales, const float* quats,

@@ -36,7 +36,18 @@ class GsConfig(ctypes.Structure):
     _fields_ = [("alpha_min", c_f), ("alpha_max", c_f), ("t_min_fwd", c_f), ("t_min_bwd", c_f),
                 ("eps2d", c_f), ("sh_degree", c_i), ("fb_format", c_i), ("fb_round", c_i),
                 ("reduce_mode", c_i), ("reduce_threshold", c_i), ("flags", c_i),
-                ("background", c_f * 3), ("reserved", c_i * 2)]
+                ("background", c_f * 3), ("n_views", c_i), ("reserved", c_i * 1)]
+
+
+MAX_VIEWS = 16
+
+
+def camera_array(cams) -> ctypes.Array:
+    """A C array of gs_camera for the view-batched entry points (cam points to n_views cameras)."""
+    arr = (GsCamera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c
+    return arr
 
 
 STATS_FIELDS = ["fwd_queued", "fwd_evaluated", "fwd_covered", "bwd_queued", "bwd_evaluated",
@@ -68,6 +79,7 @@ _SIGS = {
     "gs_prepare_2d": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                      c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_sort": (ctypes.c_int, [c_i, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_sort_views": (ctypes.c_int, [c_i, c_i, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_raster_setup": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                        c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_raster_fwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
@@ -119,6 +131,11 @@ def _ptr(t):
     return t.data_ptr()
 
 
+def _cam(cam):
+    """A gs_camera* argument from one GsCamera or a camera_array()."""
+    return cam if isinstance(cam, ctypes.Array) else ctypes.byref(cam)
+
+
 def _check(name, rc):
     if rc != 0:
         msg = lib().gs_last_error()
@@ -152,7 +169,7 @@ def gs_framebuffer_size(width, height, fb_format) -> int:
 def gs_preprocess(cam: GsCamera, cfg: GsConfig, n, means3d, scales, quats, opacities, sh,
                   means2d, conics, rgb, depth, keys, ids, n_visible, ws, ws_bytes, stream):
     _check("gs_preprocess", lib().gs_preprocess(
-        ctypes.byref(cam), ctypes.byref(cfg), n, _ptr(means3d), _ptr(scales), _ptr(quats),
+        _cam(cam), ctypes.byref(cfg), n, _ptr(means3d), _ptr(scales), _ptr(quats),
         _ptr(opacities), _ptr(sh), _ptr(means2d), _ptr(conics), _ptr(rgb), _ptr(depth),
         _ptr(keys), _ptr(ids), _ptr(n_visible), _ptr(ws), ws_bytes, stream))
 
@@ -167,6 +184,11 @@ def gs_prepare_2d(cam: GsCamera, cfg: GsConfig, n, means2d, conics, opacities, d
 def gs_sort(n, keys, ids, n_visible, ws, ws_bytes, stream):
     _check("gs_sort", lib().gs_sort(n, _ptr(keys), _ptr(ids), _ptr(n_visible), _ptr(ws),
                                     ws_bytes, stream))
+
+
+def gs_sort_views(n_views, n, keys, ids, n_visible, ws, ws_bytes, stream):
+    _check("gs_sort_views", lib().gs_sort_views(n_views, n, _ptr(keys), _ptr(ids), _ptr(n_visible),
+                                                _ptr(ws), ws_bytes, stream))
 
 
 def gs_raster_setup(cam: GsCamera, cfg: GsConfig, n, sorted_ids, n_visible, means2d, conics,
@@ -198,7 +220,7 @@ def gs_preprocess_bwd(cam: GsCamera, cfg: GsConfig, n, means3d, scales, quats, o
                       dL_dmeans2d, dL_dconics, dL_drgb, dL_dopacities2d, dL_dmeans3d, dL_dscales,
                       dL_dquats, dL_dopacities, dL_dsh, stream):
     _check("gs_preprocess_bwd", lib().gs_preprocess_bwd(
-        ctypes.byref(cam), ctypes.byref(cfg), n, _ptr(means3d), _ptr(scales), _ptr(quats),
+        _cam(cam), ctypes.byref(cfg), n, _ptr(means3d), _ptr(scales), _ptr(quats),
         _ptr(opacities), _ptr(sh), _ptr(dL_dmeans2d), _ptr(dL_dconics), _ptr(dL_drgb),
         _ptr(dL_dopacities2d), _ptr(dL_dmeans3d), _ptr(dL_dscales), _ptr(dL_dquats),
         _ptr(dL_dopacities), _ptr(dL_dsh), stream))

@@ -90,8 +90,12 @@ int check_cfg(const gs_config* c) {
     for (int k = 0; k < 3; ++k)
         if (!isfinite(c->background[k]))
             return fail(GS_ERR_INVALID_ARGUMENT, "background must be finite");
+    if (c->n_views < 0 || c->n_views > GS_MAX_VIEWS)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_views %d outside 0..%d", c->n_views, GS_MAX_VIEWS);
     return GS_OK;
 }
+
+
 
 #define GSR_TRY(x)                \
     do {                          \
@@ -109,6 +113,51 @@ int check_ws(void* ws, size_t have, size_t need) {
     if (!ws) return fail(GS_ERR_INVALID_ARGUMENT, "workspace is NULL (%zu bytes needed)", need);
     if (have < need)
         return fail(GS_ERR_CAPACITY, "workspace has %zu bytes, %zu needed", have, need);
+    if (((uintptr_t)ws) % 256 != 0) return fail(GS_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+    return GS_OK;
+}
+
+int views_of(const gs_config* c) { return (c && c->n_views > 1) ? c->n_views : 1; }
+
+int check_one_view(const gs_config* c, const char* what) {
+    if (views_of(c) != 1)
+        return fail(GS_ERR_UNSUPPORTED, "%s processes one view per call (n_views = %d)", what,
+                    c->n_views);
+    return GS_OK;
+}
+
+// V cameras of one image size, each valid.
+int check_cams(const gs_camera* cam, int V) {
+    if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
+    for (int v = 0; v < V; ++v) {
+        GSR_TRY(check_cam(cam + v));
+        if (cam[v].width != cam[0].width || cam[v].height != cam[0].height)
+            return fail(GS_ERR_INVALID_ARGUMENT, "camera %d is %d x %d, camera 0 %d x %d: the views "
+                        "of one call share the image size", v, cam[v].width, cam[v].height,
+                        cam[0].width, cam[0].height);
+    }
+    return GS_OK;
+}
+
+gsr::CamSet cam_set(const gs_camera* cam, int V) {
+    gsr::CamSet cs{};
+    for (int v = 0; v < V; ++v) cs.c[v] = gsr::make_cam(cam[v]);
+    return cs;
+}
+
+// The per-view slab of a V-view call: ws_bytes / V rounded down to 256 bytes.
+size_t slab_of(size_t ws_bytes, int V) { return V > 1 ? (ws_bytes / (size_t)V) / 256 * 256 : ws_bytes; }
+
+// Checks that each of the V slabs holds `need` bytes; the views' Views descriptor.
+int check_ws_views(void* ws, size_t ws_bytes, size_t need, int V, gsr::Views& out) {
+    out.count = V;
+    out.ws = V > 1 ? slab_of(ws_bytes, V) : 0;
+    if (need == 0) return GS_OK;
+    if (V == 1) return check_ws(ws, ws_bytes, need);
+    if (!ws) return fail(GS_ERR_INVALID_ARGUMENT, "workspace is NULL (%d x %zu bytes needed)", V, need);
+    if (slab_of(ws_bytes, V) < need)
+        return fail(GS_ERR_CAPACITY, "workspace slab per view has %zu bytes, %zu needed",
+                    slab_of(ws_bytes, V), need);
     if (((uintptr_t)ws) % 256 != 0) return fail(GS_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
     return GS_OK;
 }
@@ -157,10 +206,7 @@ size_t gs_framebuffer_size(int32_t width, int32_t height, int32_t fb_format) {
     return (size_t)width * height * gsr::fb_bytes_per_pixel(fb_format);
 }
 
-size_t gs_workspace_size(int32_t op, int32_t n, int32_t width, int32_t height, const gs_config* cfg) {
-    if (n < 0 || n > MAX_N) return 0;
-    if (width < 1 || width > MAX_DIM || height < 1 || height > MAX_DIM) return 0;
-    (void)cfg;
+static size_t one_view_ws(int32_t op, int32_t n, int32_t width, int32_t height) {
     switch (op) {
     case GS_OP_PREPROCESS:
     case GS_OP_PREPARE_2D: return preprocess_ws(n);
@@ -180,25 +226,35 @@ size_t gs_workspace_size(int32_t op, int32_t n, int32_t width, int32_t height, c
     }
 }
 
+size_t gs_workspace_size(int32_t op, int32_t n, int32_t width, int32_t height, const gs_config* cfg) {
+    if (n < 0 || n > MAX_N) return 0;
+    if (width < 1 || width > MAX_DIM || height < 1 || height > MAX_DIM) return 0;
+    if (cfg && (cfg->n_views < 0 || cfg->n_views > GS_MAX_VIEWS)) return 0;
+    const int V = views_of(cfg);
+    const size_t one = one_view_ws(op, n, width, height);
+    return V == 1 ? one : (size_t)V * gsr::align_up(one);
+}
+
 int gs_preprocess(const gs_camera* cam, const gs_config* cfg, int32_t n, const float* means3d,
                   const float* scales, const float* quats, const float* opacities, const float* sh,
                   float* means2d, float* conics, float* rgb, float* depth, uint32_t* keys,
                   int32_t* ids, int32_t* n_visible, void* ws, size_t ws_bytes, void* stream) {
-    GSR_TRY(check_cam(cam));
     GSR_TRY(check_cfg(cfg));
+    const int V = views_of(cfg);
+    GSR_TRY(check_cams(cam, V));
     GSR_TRY(check_n(n));
     GSR_NEED(n_visible);
+    gsr::Views vs{V, 0};
     if (n > 0) {
         GSR_NEED(means3d); GSR_NEED(scales); GSR_NEED(quats); GSR_NEED(opacities); GSR_NEED(sh);
         GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(rgb); GSR_NEED(depth); GSR_NEED(keys);
         GSR_NEED(ids);
         GSR_TRY(check_align16(sh, "sh"));
-        GSR_TRY(check_ws(ws, ws_bytes, preprocess_ws(n)));
+        GSR_TRY(check_ws_views(ws, ws_bytes, preprocess_ws(n), V, vs));
     }
-    const gsr::CamDev cd = gsr::make_cam(*cam);
-    return hip_status(gsr::launch_preprocess(cd, *cfg, n, means3d, scales, quats, opacities, sh,
-                                             means2d, conics, rgb, depth, keys, ids, n_visible, ws,
-                                             (hipStream_t)stream),
+    return hip_status(gsr::launch_preprocess(cam_set(cam, V), vs, *cfg, n, means3d, scales, quats,
+                                             opacities, sh, means2d, conics, rgb, depth, keys, ids,
+                                             n_visible, ws, (hipStream_t)stream),
                       "gs_preprocess");
 }
 
@@ -208,6 +264,7 @@ int gs_prepare_2d(const gs_camera* cam, const gs_config* cfg, int32_t n, const f
     if (!cam) return fail(GS_ERR_INVALID_ARGUMENT, "camera is NULL");
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_one_view(cfg, "gs_prepare_2d"));
     GSR_TRY(check_n(n));
     GSR_NEED(n_visible);
     if (n > 0) {
@@ -233,6 +290,21 @@ int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible, v
                       "gs_sort");
 }
 
+int gs_sort_views(int32_t n_views, int32_t n, uint32_t* keys, int32_t* ids,
+                  const int32_t* n_visible, void* ws, size_t ws_bytes, void* stream) {
+    if (n_views < 1 || n_views > GS_MAX_VIEWS)
+        return fail(GS_ERR_INVALID_ARGUMENT, "n_views %d outside 1..%d", n_views, GS_MAX_VIEWS);
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    if (n == 0) return ok();
+    GSR_NEED(keys);
+    GSR_NEED(ids);
+    gsr::Views vs{n_views, 0};
+    GSR_TRY(check_ws_views(ws, ws_bytes, gsr::sort_ws_bytes(n, 4), n_views, vs));
+    return hip_status(gsr::launch_sort_u32(n, keys, ids, n_visible, ws, (hipStream_t)stream, vs),
+                      "gs_sort_views");
+}
+
 int gs_raster_setup(const gs_camera* cam, const gs_config* cfg, int32_t n, const int32_t* sorted_ids,
                     const int32_t* n_visible, const float* means2d, const float* conics,
                     const float* opacities, const float* rgb, void* ws, size_t ws_bytes,
@@ -245,10 +317,12 @@ int gs_raster_setup(const gs_camera* cam, const gs_config* cfg, int32_t n, const
     if (n > 0) {
         GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
     }
-    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, false)));
+    gsr::Views vs{1, 0};
+    GSR_TRY(check_ws_views(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, false),
+                           views_of(cfg), vs));
     return hip_status(gsr::launch_raster_setup(*cfg, cam->width, cam->height, n, sorted_ids,
                                                n_visible, means2d, conics, opacities, rgb, ws,
-                                               (hipStream_t)stream),
+                                               (hipStream_t)stream, vs),
                       "gs_raster_setup");
 }
 
@@ -265,11 +339,13 @@ int gs_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const i
     if (n > 0) {
         GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
     }
-    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, false)));
+    gsr::Views vs{1, 0};
+    GSR_TRY(check_ws_views(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, false),
+                           views_of(cfg), vs));
     return hip_status(gsr::launch_raster_fwd(*cfg, cam->width, cam->height, n, sorted_ids,
                                              n_visible, means2d, conics, opacities, rgb, fb,
                                              out_rgb, out_T, out_coverage, stats, ws,
-                                             (hipStream_t)stream),
+                                             (hipStream_t)stream, vs),
                       "gs_raster_fwd");
 }
 
@@ -290,12 +366,14 @@ int gs_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, const i
         GSR_NEED(sorted_ids); GSR_NEED(means2d); GSR_NEED(conics); GSR_NEED(opacities); GSR_NEED(rgb);
         GSR_NEED(dL_dmeans2d); GSR_NEED(dL_dconics); GSR_NEED(dL_dopacities); GSR_NEED(dL_drgb);
     }
-    GSR_TRY(check_ws(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, true)));
+    gsr::Views vs{1, 0};
+    GSR_TRY(check_ws_views(ws, ws_bytes, gsr::raster_ws_bytes(n, cam->width, cam->height, true),
+                           views_of(cfg), vs));
     return hip_status(gsr::launch_raster_bwd(*cfg, cam->width, cam->height, n, sorted_ids,
                                              n_visible, means2d, conics, opacities, rgb, fb,
                                              dL_dimage, dL_dmeans2d, dL_dconics, dL_dopacities,
                                              dL_drgb, dL_dT, dL_dbackground, out_live, stats, ws,
-                                             (hipStream_t)stream),
+                                             (hipStream_t)stream, vs),
                       "gs_raster_bwd");
 }
 
@@ -305,8 +383,9 @@ int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, con
                       const float* dL_drgb, const float* dL_dopacities2d, float* dL_dmeans3d,
                       float* dL_dscales, float* dL_dquats, float* dL_dopacities, float* dL_dsh,
                       void* stream) {
-    GSR_TRY(check_cam(cam));
     GSR_TRY(check_cfg(cfg));
+    const int V = views_of(cfg);
+    GSR_TRY(check_cams(cam, V));
     GSR_TRY(check_n(n));
     if (n == 0) return ok();
     GSR_NEED(means3d); GSR_NEED(scales); GSR_NEED(quats); GSR_NEED(opacities); GSR_NEED(sh);
@@ -315,8 +394,7 @@ int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, con
     GSR_NEED(dL_dsh);
     GSR_TRY(check_align16(sh, "sh"));
     GSR_TRY(check_align16(dL_dsh, "dL_dsh"));
-    const gsr::CamDev cd = gsr::make_cam(*cam);
-    return hip_status(gsr::launch_preprocess_bwd(cd, *cfg, n, means3d, scales, quats, opacities, sh,
+    return hip_status(gsr::launch_preprocess_bwd(cam_set(cam, V), V, *cfg, n, means3d, scales, quats, opacities, sh,
                                                  dL_dmeans2d, dL_dconics, dL_drgb, dL_dopacities2d,
                                                  dL_dmeans3d, dL_dscales, dL_dquats, dL_dopacities,
                                                  dL_dsh, (hipStream_t)stream),
@@ -339,6 +417,7 @@ int gs_tile_prepare(const gs_camera* cam, const gs_config* cfg, int32_t n, const
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
     GSR_TRY(check_no_background(cfg));
+    GSR_TRY(check_one_view(cfg, "the tile-based baseline"));
     GSR_TRY(check_n(n));
     GSR_NEED(n_pairs);
     if (n > 0) {
@@ -360,6 +439,7 @@ int gs_tile_raster_fwd(const gs_camera* cam, const gs_config* cfg, int32_t n, co
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
     GSR_TRY(check_no_background(cfg));
+    GSR_TRY(check_one_view(cfg, "the tile-based baseline"));
     GSR_TRY(check_n(n));
     if (pair_capacity < 0 || pair_capacity > (int64_t)1 << 31)
         return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside 0..2^31");
@@ -385,6 +465,7 @@ int gs_tile_raster_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, co
     GSR_TRY(check_dims(cam->width, cam->height));
     GSR_TRY(check_cfg(cfg));
     GSR_TRY(check_no_background(cfg));
+    GSR_TRY(check_one_view(cfg, "the tile-based baseline"));
     GSR_TRY(check_n(n));
     if (pair_capacity < 0 || pair_capacity > (int64_t)1 << 31)
         return fail(GS_ERR_INVALID_ARGUMENT, "pair_capacity outside 0..2^31");

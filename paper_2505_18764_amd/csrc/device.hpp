@@ -114,6 +114,18 @@ __device__ __forceinline__ void wave_sum9(const float (&g)[9], float& a, float& 
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 
+// View-batched launches (grid y = view): p moved to this workgroup's view, where one view's part
+// of the array is `per_view` elements (view_at) or bytes (view_bytes). Null stays null.
+template <class T>
+__device__ __forceinline__ T* view_at(T* p, uint64_t per_view) {
+    return p ? p + (uint64_t)blockIdx.y * per_view : p;
+}
+template <class T>
+__device__ __forceinline__ T* view_bytes(T* p, uint64_t bytes) {
+    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uint64_t)blockIdx.y * bytes)
+             : p;
+}
+
 // ---- framebuffer formats (Sec. 3.3) -------------------------------------------------------
 
 enum : int { FB_F32 = 0, FB_F16 = 1, FB_UNORM16 = 2, FB_BF16 = 3, FB_UNORM8 = 4 };

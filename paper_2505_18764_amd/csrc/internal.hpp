@@ -21,6 +21,24 @@ struct CamDev {
 
 CamDev make_cam(const gs_camera& c);
 
+// ---- batched launches over views --------------------------------------------------------------
+// A launch over V views of one scene has grid y = V. Each per-view array of the batch is the
+// concatenation of the views' arrays ([V][n][..] by splat, [V][3][H][W] images, [V] framebuffers);
+// each view's scratch is its own slab of `ws` bytes of the workspace. Kernels move every pointer
+// by blockIdx.y times that array's per-view size (view 0 of a one-view launch moves nothing).
+constexpr int MAX_VIEWS = 16;
+
+struct CamSet {
+    CamDev c[MAX_VIEWS];
+};
+
+struct Views {
+    int count;         // V >= 1
+    uint64_t ws;       // bytes between two views' workspace slabs
+};
+
+inline Views one_view() { return Views{1, 0}; }
+
 // ---- layout of the raster workspace -------------------------------------------------------
 constexpr int TILE = 32;              // pixels per side of the tile one workgroup owns
 constexpr int REC_BYTES = 48;         // one staged splat record
@@ -57,12 +75,13 @@ size_t sort_ws_bytes(int n, int key_bytes);
 size_t compact_ws_bytes(int n);
 
 // ---- launchers (return hipError_t of the last launch) -------------------------------------
-hipError_t launch_preprocess(const CamDev& cam, const gs_config& cfg, int n, const float* means3d,
-                             const float* scales, const float* quats, const float* opac,
-                             const float* sh, float* means2d, float* conics, float* rgb,
-                             float* depth, uint32_t* keys, int32_t* ids, int32_t* n_visible,
-                             void* ws, hipStream_t s);
-hipError_t launch_preprocess_bwd(const CamDev& cam, const gs_config& cfg, int n,
+hipError_t launch_preprocess(const CamSet& cams, const Views& vs, const gs_config& cfg, int n,
+                             const float* means3d, const float* scales, const float* quats,
+                             const float* opac, const float* sh, float* means2d, float* conics,
+                             float* rgb, float* depth, uint32_t* keys, int32_t* ids,
+                             int32_t* n_visible, void* ws, hipStream_t s);
+// Sums the views' gradients: the 3D outputs are written once, after all V views.
+hipError_t launch_preprocess_bwd(const CamSet& cams, int nviews, const gs_config& cfg, int n,
                                  const float* means3d, const float* scales, const float* quats,
                                  const float* opac, const float* sh, const float* g_means2d,
                                  const float* g_conics, const float* g_rgb, const float* g_opac2d,
@@ -73,29 +92,34 @@ hipError_t launch_prepare_2d(int width, int height, const gs_config& cfg, int n,
                              const float* depth, uint32_t* keys, int32_t* ids, int32_t* n_visible,
                              void* ws, hipStream_t s);
 hipError_t launch_sort_u32(int n, uint32_t* keys, int32_t* vals, const int32_t* n_dev, void* ws,
-                           hipStream_t s);
+                           hipStream_t s, const Views& vs = one_view());
 hipError_t launch_sort_u64(int n, uint64_t* keys, int32_t* vals, const int32_t* n_dev,
                            int end_bit, void* ws, hipStream_t s);
-hipError_t launch_fill_u32(void* p, size_t count, uint32_t value, hipStream_t s);
+// Fills `count` words at p in each of `views` slabs `stride` bytes apart.
+hipError_t launch_fill_u32(void* p, size_t count, uint32_t value, hipStream_t s, int views = 1,
+                           uint64_t stride = 0);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t count, uint32_t* sums,
-                                 hipStream_t s);
+                                 hipStream_t s, const Views& vs = one_view());
 hipError_t launch_compact(int n, const uint32_t* key_by_id, uint32_t* keys, int32_t* ids,
-                          int32_t* n_visible, void* ws, hipStream_t s);
+                          int32_t* n_visible, void* ws, hipStream_t s, const Views& vs = one_view());
 hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int n,
                                const int32_t* sorted_ids, const int32_t* n_visible,
                                const float* means2d, const float* conics, const float* opac,
-                               const float* rgb, void* ws, hipStream_t s);
+                               const float* rgb, void* ws, hipStream_t s,
+                               const Views& vs = one_view());
 hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                              const int32_t* sorted_ids, const int32_t* n_visible,
                              const float* means2d, const float* conics, const float* opac,
                              const float* rgb, void* fb, float* out_rgb, float* out_T,
-                             int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s);
+                             int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s,
+                             const Views& vs = one_view());
 hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                              const int32_t* sorted_ids, const int32_t* n_visible,
                              const float* means2d, const float* conics, const float* opac,
                              const float* rgb, const void* fb, const float* dL_dimg,
                              float* g_means2d, float* g_conics, float* g_opac, float* g_rgb, const float* dL_dT, float* dL_dbg,
-                             int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s);
+                             int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s,
+                             const Views& vs = one_view());
 
 
 // ---- tile-based comparison rasterizer ------------------------------------------------------

@@ -1,5 +1,8 @@
 // preprocess.hip -- projection of 3D Gaussians to 2D splats and its backward, one thread per
 // Gaussian (Sec. 2.1.1-2.1.2 forward; Sec. 2.1.3 "dedicated subsequent pass" backward).
+// Several cameras of one scene run in one launch: the forward has grid y = view and writes each
+// view's [n] outputs; the backward walks the views in order for each Gaussian and writes the sum
+// of their gradients once.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -206,10 +209,16 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(
     int n, const float* __restrict__ means3d, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
-    CamDev cam, float amin, float eps2d, float* __restrict__ means2d,
+    const CamSet cams, float amin, float eps2d, float* __restrict__ means2d,
     float* __restrict__ conics, float* __restrict__ rgb, float* __restrict__ depth,
-    uint32_t* __restrict__ key_by_id) {
+    uint32_t* __restrict__ key_by_id, uint64_t vws) {
     constexpr int K = (DEG + 1) * (DEG + 1);
+    const CamDev& cam = cams.c[blockIdx.y];
+    means2d = view_at(means2d, 2ull * n);
+    conics = view_at(conics, 3ull * n);
+    rgb = view_at(rgb, 3ull * n);
+    depth = view_at(depth, (uint64_t)n);
+    key_by_id = view_bytes(key_by_id, vws);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
         bool vis = false;
@@ -255,7 +264,7 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     int n, const float* __restrict__ means3d, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ opac, const float* __restrict__ sh,
-    CamDev cam, float amin, float eps2d, const float* __restrict__ g_m2,
+    const CamSet cams, int nviews, float amin, float eps2d, const float* __restrict__ g_m2,
     const float* __restrict__ g_con, const float* __restrict__ g_rgb,
     const float* __restrict__ g_op2, float* __restrict__ d_m3, float* __restrict__ d_sc,
     float* __restrict__ d_q, float* __restrict__ d_op, float* __restrict__ d_sh) {
@@ -263,126 +272,129 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     if (i >= n) return;
     constexpr int K = (DEG + 1) * (DEG + 1);
     const float o = opac[i];
-    Geo g;
-    geometry(cam, amin, eps2d, cam.width, cam.height, means3d + 3 * (size_t)i,
-             scales + 3 * (size_t)i, quats + 4 * (size_t)i, o, g);
-    float* dsh = d_sh + (size_t)i * K * 3;
-    if (!g.vis) {
-        for (int j = 0; j < 3; ++j) { d_m3[3 * (size_t)i + j] = 0.f; d_sc[3 * (size_t)i + j] = 0.f; }
-        for (int j = 0; j < 4; ++j) d_q[4 * (size_t)i + j] = 0.f;
-        d_op[i] = 0.f;
-        float z[3 * K];
+    // sums over the views, in view order; a view that culls the splat adds nothing
+    float a_m3[3] = {0.f, 0.f, 0.f}, a_sc[3] = {0.f, 0.f, 0.f}, a_q[4] = {0.f, 0.f, 0.f, 0.f};
+    float a_op = 0.f;
+    float a_sh[3 * K];
 #pragma unroll
-        for (int j = 0; j < 3 * K; ++j) z[j] = 0.f;
-        store_coeffs<3 * K>(dsh, z);
-        return;
-    }
-    // ---- conic -> Sigma_2D: G2 = -C Ghat C, Ghat = [[ga, gb/2], [gb/2, gc]] ----------------
-    const float ga = g_con[3 * (size_t)i], gb = g_con[3 * (size_t)i + 1], gc = g_con[3 * (size_t)i + 2];
-    const float a = g.ca, b = g.cb, c = g.cc;
-    const float P00 = ga * a + 0.5f * gb * b, P01 = ga * b + 0.5f * gb * c;
-    const float P10 = 0.5f * gb * a + gc * b, P11 = 0.5f * gb * b + gc * c;
-    const float G00 = -(a * P00 + b * P10);
-    const float G01 = -0.5f * ((a * P01 + b * P11) + (b * P00 + c * P10));
-    const float G11 = -(b * P01 + c * P11);
-    // ---- Sigma_2D = T S T^T: dL/dT = 2 G2 T S, dL/dS = T^T G2 T ---------------------------
-    const float* T = g.T;
-    const float* S = g.S3;
-    float Sm[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
-    float TS[6];   // T S (2x3)
-    for (int r = 0; r < 2; ++r)
-        for (int j = 0; j < 3; ++j)
-            TS[3 * r + j] = T[3 * r] * Sm[j] + T[3 * r + 1] * Sm[3 + j] + T[3 * r + 2] * Sm[6 + j];
-    float dT[6];
-    for (int j = 0; j < 3; ++j) {
-        dT[j] = 2.f * (G00 * TS[j] + G01 * TS[3 + j]);
-        dT[3 + j] = 2.f * (G01 * TS[j] + G11 * TS[3 + j]);
-    }
-    float dS[9];
-    for (int k = 0; k < 3; ++k)
-        for (int l = 0; l < 3; ++l)
-            dS[3 * k + l] = T[k] * (G00 * T[l] + G01 * T[3 + l]) +
-                            T[3 + k] * (G01 * T[l] + G11 * T[3 + l]);
-    // ---- Sigma_3D = M M^T, M = R diag(s): dL/dM = 2 dS M ----------------------------------
-    const float* R = g.R;
-    const float s[3] = {scales[3 * (size_t)i], scales[3 * (size_t)i + 1], scales[3 * (size_t)i + 2]};
-    float dM[9];
-    for (int r = 0; r < 3; ++r)
-        for (int j = 0; j < 3; ++j)
-            dM[3 * r + j] = 2.f * (dS[3 * r] * R[j] + dS[3 * r + 1] * R[3 + j] +
-                                   dS[3 * r + 2] * R[6 + j]) * s[j];
-    float dR[9];
-    for (int r = 0; r < 3; ++r)
-        for (int j = 0; j < 3; ++j) dR[3 * r + j] = dM[3 * r + j] * s[j];
-    for (int j = 0; j < 3; ++j)
-        d_sc[3 * (size_t)i + j] = dM[j] * R[j] + dM[3 + j] * R[3 + j] + dM[6 + j] * R[6 + j];
-    // ---- R(q): derivatives of the nine entries w.r.t. the unit quaternion -------------------
-    const float w = g.qw, x = g.qx, y = g.qy, z = g.qz;
-    float dw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    float dx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] +
-                      w * dR[7] - 2.f * x * dR[8]);
-    float dy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
-                      z * dR[7] - 2.f * y * dR[8]);
-    float dz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
-                      y * dR[5] + x * dR[6] + y * dR[7]);
-    // through the normalisation q / |q|
-    const float dot = w * dw + x * dx + y * dy + z * dz;
-    const float iqn = 1.0f / g.qn;
-    d_q[4 * (size_t)i] = (dw - w * dot) * iqn;
-    d_q[4 * (size_t)i + 1] = (dx - x * dot) * iqn;
-    d_q[4 * (size_t)i + 2] = (dy - y * dot) * iqn;
-    d_q[4 * (size_t)i + 3] = (dz - z * dot) * iqn;
-    // ---- T = J W and mean2d: gradient w.r.t. camera coordinates -----------------------------
-    const float dJ00 = dT[0] * cam.R[0] + dT[1] * cam.R[1] + dT[2] * cam.R[2];
-    const float dJ02 = dT[0] * cam.R[6] + dT[1] * cam.R[7] + dT[2] * cam.R[8];
-    const float dJ11 = dT[3] * cam.R[3] + dT[4] * cam.R[4] + dT[5] * cam.R[5];
-    const float dJ12 = dT[3] * cam.R[6] + dT[4] * cam.R[7] + dT[5] * cam.R[8];
-    const float iz = 1.0f / g.tz, iz2 = iz * iz, iz3 = iz2 * iz;
-    const float gmx = g_m2[2 * (size_t)i], gmy = g_m2[2 * (size_t)i + 1];
-    float dtx = dJ02 * (-cam.fx * iz2) + gmx * cam.fx * iz;
-    float dty = dJ12 * (-cam.fy * iz2) + gmy * cam.fy * iz;
-    float dtz = dJ00 * (-cam.fx * iz2) + dJ02 * (2.f * cam.fx * g.tx * iz3) +
-                dJ11 * (-cam.fy * iz2) + dJ12 * (2.f * cam.fy * g.ty * iz3) -
-                gmx * cam.fx * g.tx * iz2 - gmy * cam.fy * g.ty * iz2;
-    float dmx = cam.R[0] * dtx + cam.R[3] * dty + cam.R[6] * dtz;
-    float dmy = cam.R[1] * dtx + cam.R[4] * dty + cam.R[7] * dtz;
-    float dmz = cam.R[2] * dtx + cam.R[5] * dty + cam.R[8] * dtz;
-    // ---- SH colour: coefficients and the view-direction term ---------------------------------
-    float vx = means3d[3 * (size_t)i] - cam.campos[0];
-    float vy = means3d[3 * (size_t)i + 1] - cam.campos[1];
-    float vz = means3d[3 * (size_t)i + 2] - cam.campos[2];
-    const float il = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
-    const float ux = vx * il, uy = vy * il, uz = vz * il;
-    float Y[16];
-    sh_eval(ux, uy, uz, DEG, Y);
+    for (int j = 0; j < 3 * K; ++j) a_sh[j] = 0.f;
     float co[3 * K];
     load_coeffs<3 * K>(sh + (size_t)i * (3 * K), co);
-    float val[3] = {0.5f, 0.5f, 0.5f};
+    for (int v = 0; v < nviews; ++v) {
+        const CamDev& cam = cams.c[v];
+        const size_t vi = (size_t)v * n + i;    // this Gaussian in view v's [n] arrays
+        Geo g;
+        geometry(cam, amin, eps2d, cam.width, cam.height, means3d + 3 * (size_t)i,
+                 scales + 3 * (size_t)i, quats + 4 * (size_t)i, o, g);
+        if (!g.vis) continue;
+        // ---- conic -> Sigma_2D: G2 = -C Ghat C, Ghat = [[ga, gb/2], [gb/2, gc]] ----------------
+        const float ga = g_con[3 * vi], gb = g_con[3 * vi + 1], gc = g_con[3 * vi + 2];
+        const float a = g.ca, b = g.cb, c = g.cc;
+        const float P00 = ga * a + 0.5f * gb * b, P01 = ga * b + 0.5f * gb * c;
+        const float P10 = 0.5f * gb * a + gc * b, P11 = 0.5f * gb * b + gc * c;
+        const float G00 = -(a * P00 + b * P10);
+        const float G01 = -0.5f * ((a * P01 + b * P11) + (b * P00 + c * P10));
+        const float G11 = -(b * P01 + c * P11);
+        // ---- Sigma_2D = T S T^T: dL/dT = 2 G2 T S, dL/dS = T^T G2 T ---------------------------
+        const float* T = g.T;
+        const float* S = g.S3;
+        float Sm[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+        float TS[6];   // T S (2x3)
+        for (int r = 0; r < 2; ++r)
+            for (int j = 0; j < 3; ++j)
+                TS[3 * r + j] = T[3 * r] * Sm[j] + T[3 * r + 1] * Sm[3 + j] + T[3 * r + 2] * Sm[6 + j];
+        float dT[6];
+        for (int j = 0; j < 3; ++j) {
+            dT[j] = 2.f * (G00 * TS[j] + G01 * TS[3 + j]);
+            dT[3 + j] = 2.f * (G01 * TS[j] + G11 * TS[3 + j]);
+        }
+        float dS[9];
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                dS[3 * k + l] = T[k] * (G00 * T[l] + G01 * T[3 + l]) +
+                                T[3 + k] * (G01 * T[l] + G11 * T[3 + l]);
+        // ---- Sigma_3D = M M^T, M = R diag(s): dL/dM = 2 dS M ----------------------------------
+        const float* R = g.R;
+        const float s[3] = {scales[3 * (size_t)i], scales[3 * (size_t)i + 1], scales[3 * (size_t)i + 2]};
+        float dM[9];
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 3; ++j)
+                dM[3 * r + j] = 2.f * (dS[3 * r] * R[j] + dS[3 * r + 1] * R[3 + j] +
+                                       dS[3 * r + 2] * R[6 + j]) * s[j];
+        float dR[9];
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 3; ++j) dR[3 * r + j] = dM[3 * r + j] * s[j];
+        for (int j = 0; j < 3; ++j)
+            a_sc[j] += dM[j] * R[j] + dM[3 + j] * R[3 + j] + dM[6 + j] * R[6 + j];
+        // ---- R(q): derivatives of the nine entries w.r.t. the unit quaternion -------------------
+        const float w = g.qw, x = g.qx, y = g.qy, z = g.qz;
+        float dw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+        float dx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] +
+                          w * dR[7] - 2.f * x * dR[8]);
+        float dy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                          z * dR[7] - 2.f * y * dR[8]);
+        float dz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
+                          y * dR[5] + x * dR[6] + y * dR[7]);
+        // through the normalisation q / |q|
+        const float dot = w * dw + x * dx + y * dy + z * dz;
+        const float iqn = 1.0f / g.qn;
+        a_q[0] += (dw - w * dot) * iqn;
+        a_q[1] += (dx - x * dot) * iqn;
+        a_q[2] += (dy - y * dot) * iqn;
+        a_q[3] += (dz - z * dot) * iqn;
+        // ---- T = J W and mean2d: gradient w.r.t. camera coordinates -----------------------------
+        const float dJ00 = dT[0] * cam.R[0] + dT[1] * cam.R[1] + dT[2] * cam.R[2];
+        const float dJ02 = dT[0] * cam.R[6] + dT[1] * cam.R[7] + dT[2] * cam.R[8];
+        const float dJ11 = dT[3] * cam.R[3] + dT[4] * cam.R[4] + dT[5] * cam.R[5];
+        const float dJ12 = dT[3] * cam.R[6] + dT[4] * cam.R[7] + dT[5] * cam.R[8];
+        const float iz = 1.0f / g.tz, iz2 = iz * iz, iz3 = iz2 * iz;
+        const float gmx = g_m2[2 * vi], gmy = g_m2[2 * vi + 1];
+        float dtx = dJ02 * (-cam.fx * iz2) + gmx * cam.fx * iz;
+        float dty = dJ12 * (-cam.fy * iz2) + gmy * cam.fy * iz;
+        float dtz = dJ00 * (-cam.fx * iz2) + dJ02 * (2.f * cam.fx * g.tx * iz3) +
+                    dJ11 * (-cam.fy * iz2) + dJ12 * (2.f * cam.fy * g.ty * iz3) -
+                    gmx * cam.fx * g.tx * iz2 - gmy * cam.fy * g.ty * iz2;
+        float dmx = cam.R[0] * dtx + cam.R[3] * dty + cam.R[6] * dtz;
+        float dmy = cam.R[1] * dtx + cam.R[4] * dty + cam.R[7] * dtz;
+        float dmz = cam.R[2] * dtx + cam.R[5] * dty + cam.R[8] * dtz;
+        // ---- SH colour: coefficients and the view-direction term ---------------------------------
+        float vx = means3d[3 * (size_t)i] - cam.campos[0];
+        float vy = means3d[3 * (size_t)i + 1] - cam.campos[1];
+        float vz = means3d[3 * (size_t)i + 2] - cam.campos[2];
+        const float il = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+        const float ux = vx * il, uy = vy * il, uz = vz * il;
+        float Y[16];
+        sh_eval(ux, uy, uz, DEG, Y);
+        float val[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) val[ch] += Y[k] * co[3 * k + ch];
-    float gv[3];
-    for (int ch = 0; ch < 3; ++ch) gv[ch] = val[ch] > 0.f ? g_rgb[3 * (size_t)i + ch] : 0.f;
-    float wY[16], dc[3 * K];
+        for (int k = 0; k < K; ++k)
+            for (int ch = 0; ch < 3; ++ch) val[ch] += Y[k] * co[3 * k + ch];
+        float gv[3];
+        for (int ch = 0; ch < 3; ++ch) gv[ch] = val[ch] > 0.f ? g_rgb[3 * vi + ch] : 0.f;
+        float wY[16];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        dc[3 * k] = gv[0] * Y[k];
-        dc[3 * k + 1] = gv[1] * Y[k];
-        dc[3 * k + 2] = gv[2] * Y[k];
-        wY[k] = gv[0] * co[3 * k] + gv[1] * co[3 * k + 1] + gv[2] * co[3 * k + 2];
+        for (int k = 0; k < K; ++k) {
+            a_sh[3 * k] += gv[0] * Y[k];
+            a_sh[3 * k + 1] += gv[1] * Y[k];
+            a_sh[3 * k + 2] += gv[2] * Y[k];
+            wY[k] = gv[0] * co[3 * k] + gv[1] * co[3 * k + 1] + gv[2] * co[3 * k + 2];
+        }
+#pragma unroll
+        for (int k = K; k < 16; ++k) wY[k] = 0.f;
+        const float3 gd = sh_grad_dir(ux, uy, uz, DEG, wY);
+        const float dd = gd.x * ux + gd.y * uy + gd.z * uz;
+        dmx += (gd.x - ux * dd) * il;
+        dmy += (gd.y - uy * dd) * il;
+        dmz += (gd.z - uz * dd) * il;
+        a_m3[0] += dmx;
+        a_m3[1] += dmy;
+        a_m3[2] += dmz;
+        a_op += g_op2[vi];
     }
-    store_coeffs<3 * K>(dsh, dc);
-#pragma unroll
-    for (int k = K; k < 16; ++k) wY[k] = 0.f;
-    const float3 gd = sh_grad_dir(ux, uy, uz, DEG, wY);
-    const float dd = gd.x * ux + gd.y * uy + gd.z * uz;
-    dmx += (gd.x - ux * dd) * il;
-    dmy += (gd.y - uy * dd) * il;
-    dmz += (gd.z - uz * dd) * il;
-    d_m3[3 * (size_t)i] = dmx;
-    d_m3[3 * (size_t)i + 1] = dmy;
-    d_m3[3 * (size_t)i + 2] = dmz;
-    d_op[i] = g_op2[i];
+    for (int j = 0; j < 3; ++j) { d_m3[3 * (size_t)i + j] = a_m3[j]; d_sc[3 * (size_t)i + j] = a_sc[j]; }
+    for (int j = 0; j < 4; ++j) d_q[4 * (size_t)i + j] = a_q[j];
+    d_op[i] = a_op;
+    store_coeffs<3 * K>(d_sh + (size_t)i * K * 3, a_sh);
 }
 
 // Keys for splats that arrive already projected: order-preserving uint32 of the fp32 depth;
@@ -412,18 +424,21 @@ __global__ __launch_bounds__(256) void k_prepare_2d(
     }
 }
 
-__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t count, uint32_t value) {
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t count, uint32_t value,
+                           uint64_t stride) {
+    p = view_bytes(p, stride);
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (size_t)gridDim.x * blockDim.x)
         p[i] = value;
 }
 
-hipError_t launch_fill_u32(void* p, size_t count, uint32_t value, hipStream_t s) {
+hipError_t launch_fill_u32(void* p, size_t count, uint32_t value, hipStream_t s, int views,
+                           uint64_t stride) {
     if (count == 0) return hipSuccess;
     size_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, count,
-                       value);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks, views), dim3(256), 0, s, (uint32_t*)p,
+                       count, value, stride);
     return hipGetLastError();
 }
 
@@ -441,25 +456,26 @@ CamDev make_cam(const gs_camera& c) {
     return d;
 }
 
-hipError_t launch_preprocess(const CamDev& cam, const gs_config& cfg, int n, const float* means3d,
-                             const float* scales, const float* quats, const float* opac,
-                             const float* sh, float* means2d, float* conics, float* rgb,
-                             float* depth, uint32_t* keys, int32_t* ids, int32_t* n_visible,
-                             void* ws, hipStream_t s) {
-    if (n == 0) return launch_fill_u32(n_visible, 1, 0u, s);
+hipError_t launch_preprocess(const CamSet& cams, const Views& vs, const gs_config& cfg, int n,
+                             const float* means3d, const float* scales, const float* quats,
+                             const float* opac, const float* sh, float* means2d, float* conics,
+                             float* rgb, float* depth, uint32_t* keys, int32_t* ids,
+                             int32_t* n_visible, void* ws, hipStream_t s) {
+    if (n == 0) return launch_fill_u32(n_visible, (size_t)vs.count, 0u, s);
     uint32_t* key_by_id = (uint32_t*)ws;
     void* rest = (char*)ws + align_up((size_t)n * 4);
     decltype(&k_preprocess<3>) k = cfg.sh_degree == 0 ? k_preprocess<0>
                                   : cfg.sh_degree == 1 ? k_preprocess<1>
                                   : cfg.sh_degree == 2 ? k_preprocess<2> : k_preprocess<3>;
-    hipLaunchKernelGGL(k, dim3((n + 255) / 256), dim3(256), 0, s, n, means3d, scales, quats, opac,
-                       sh, cam, cfg.alpha_min, cfg.eps2d, means2d, conics, rgb, depth, key_by_id);
+    hipLaunchKernelGGL(k, dim3((n + 255) / 256, vs.count), dim3(256), 0, s, n, means3d, scales,
+                       quats, opac, sh, cams, cfg.alpha_min, cfg.eps2d, means2d, conics, rgb, depth,
+                       key_by_id, vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_compact(n, key_by_id, keys, ids, n_visible, rest, s);
+    return launch_compact(n, key_by_id, keys, ids, n_visible, rest, s, vs);
 }
 
-hipError_t launch_preprocess_bwd(const CamDev& cam, const gs_config& cfg, int n,
+hipError_t launch_preprocess_bwd(const CamSet& cams, int nviews, const gs_config& cfg, int n,
                                  const float* means3d, const float* scales, const float* quats,
                                  const float* opac, const float* sh, const float* g_means2d,
                                  const float* g_conics, const float* g_rgb, const float* g_opac2d,
@@ -470,8 +486,8 @@ hipError_t launch_preprocess_bwd(const CamDev& cam, const gs_config& cfg, int n,
                                       : cfg.sh_degree == 1 ? k_preprocess_bwd<1>
                                       : cfg.sh_degree == 2 ? k_preprocess_bwd<2> : k_preprocess_bwd<3>;
     hipLaunchKernelGGL(k, dim3((n + 255) / 256), dim3(256), 0, s, n, means3d, scales, quats, opac,
-                       sh, cam, cfg.alpha_min, cfg.eps2d, g_means2d, g_conics, g_rgb, g_opac2d,
-                       d_means3d, d_scales, d_quats, d_opac, d_sh);
+                       sh, cams, nviews, cfg.alpha_min, cfg.eps2d, g_means2d, g_conics, g_rgb,
+                       g_opac2d, d_means3d, d_scales, d_quats, d_opac, d_sh);
     return hipGetLastError();
 }
 

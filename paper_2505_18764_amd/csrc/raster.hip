@@ -113,10 +113,15 @@ __device__ void bucket_order(const uint32_t* __restrict__ w, int count, uint32_t
 __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
     const uint32_t* __restrict__ weights, int ntiles, int32_t* __restrict__ order, int split,
     int32_t* __restrict__ tile_k, int32_t* __restrict__ tile_first,
-    unsigned long long* __restrict__ counters) {
+    unsigned long long* __restrict__ counters, uint64_t vws) {
     __shared__ uint32_t s_hist[NBUCKETS];
     __shared__ unsigned long long s_tot;
     __shared__ uint32_t s_max;
+    weights = view_bytes(weights, vws);
+    order = view_bytes(order, vws);
+    tile_k = view_bytes(tile_k, vws);
+    tile_first = view_bytes(tile_first, vws);
+    counters = view_bytes(counters, vws);
     const int tid = threadIdx.x;
     if (tid == 0) { s_tot = 0ull; s_max = 0u; }
     __syncthreads();
@@ -174,7 +179,13 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
 __global__ __launch_bounds__(64) void k_plan_cuts(
     const uint32_t* __restrict__ weights, const uint16_t* __restrict__ colcnt, int wpr, int ntiles,
     const int32_t* __restrict__ tile_k, const int32_t* __restrict__ tile_first,
-    int4* __restrict__ items, uint32_t* __restrict__ item_w) {
+    int4* __restrict__ items, uint32_t* __restrict__ item_w, uint64_t vws) {
+    weights = view_bytes(weights, vws);
+    colcnt = view_bytes(colcnt, vws);
+    tile_k = view_bytes(tile_k, vws);
+    tile_first = view_bytes(tile_first, vws);
+    items = view_bytes(items, vws);
+    item_w = view_bytes(item_w, vws);
     const int t = blockIdx.x, lane = threadIdx.x;
     const int k = tile_k[t], f = tile_first[t];
     const uint32_t w = weights[t];
@@ -224,9 +235,12 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
 // One workgroup: items heaviest first; item_order padded with -1 to 2 ntiles.
 __global__ __launch_bounds__(NBUCKETS) void k_plan_items(
     const uint32_t* __restrict__ item_w, int ntiles, const unsigned long long* __restrict__ counters,
-    int32_t* __restrict__ item_order) {
+    int32_t* __restrict__ item_order, uint64_t vws) {
     __shared__ uint32_t s_hist[NBUCKETS];
     __shared__ uint32_t s_max;
+    item_w = view_bytes(item_w, vws);
+    counters = view_bytes(counters, vws);
+    item_order = view_bytes(item_order, vws);
     const int cap = ITEMS_PER_TILE * ntiles;
     const int count = (int)min((unsigned long long)cap, counters[0]);
     if (threadIdx.x == 0) s_max = 0u;
@@ -261,9 +275,19 @@ __global__ __launch_bounds__(256) void k_raster_setup(
     const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
     int saturate, int tiles_x, int ntiles, Rec* __restrict__ rec, uint2* __restrict__ rect,
     uint32_t* __restrict__ weights, uint32_t* __restrict__ bits, int wpr,
-    uint16_t* __restrict__ colcnt) {
+    uint16_t* __restrict__ colcnt, uint64_t vws) {
     __shared__ uint32_t s_bits[MAX_LDS_TILES];
     __shared__ uint32_t s_cnt[MAX_LDS_TILES];
+    sorted_ids = view_at(sorted_ids, (uint64_t)n);
+    nvis_ptr = view_at(nvis_ptr, 1);
+    means2d = view_at(means2d, 2ull * n);
+    conics = view_at(conics, 3ull * n);
+    rgb = view_at(rgb, 3ull * n);          // opacities are the views' shared [n]
+    rec = view_bytes(rec, vws);
+    rect = view_bytes(rect, vws);
+    weights = view_bytes(weights, vws);
+    bits = view_bytes(bits, vws);
+    colcnt = view_bytes(colcnt, vws);
     const bool in_lds = ntiles <= MAX_LDS_TILES;
     if (in_lds)
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) { s_bits[t] = 0u; s_cnt[t] = 0u; }
@@ -493,7 +517,9 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
 // sorted positions), which writes its FP32 (C, T) to partial[slot] instead of the framebuffer.
 // Occupancy: LDS (22.8 KB per workgroup) allows 7 workgroups per CU; the second bound asks the
 // compiler for 7 waves per SIMD (<= 72 VGPRs), which measured faster than 6 with fewer spills.
-template <int RFMT, bool TCULL, bool INSTR>
+// MULTI: a launch over several views (grid y). Its per-view pointers cost scalar registers that
+// the one-view instances, whose walk pointers stay plain kernel arguments, do not pay.
+template <int RFMT, bool TCULL, bool INSTR, bool MULTI>
 __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
     const uint2* __restrict__ rect, const int32_t* __restrict__ order,
@@ -502,8 +528,17 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     float4* __restrict__ partial,
     float amin, float amax, float tmin, float bg0, float bg1, float bg2, int fb_fmt,
     void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T,
-    int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats) {
+    int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats, uint64_t vws) {
     __shared__ Walk w;
+    if constexpr (MULTI) {   // this view's walk state (its outputs are located at the write-back)
+        nvis_ptr = view_at(nvis_ptr, 1);
+        rec = view_bytes(rec, vws);
+        rect = view_bytes(rect, vws);
+        order = view_bytes(order, vws);
+        bits = view_bytes(bits, vws);
+        items = view_bytes(items, vws);
+        item_order = view_bytes(item_order, vws);
+    }
     int tile, c_begin = 0, c_end = wpr, slot = -1;
     if (items) {
         const int it = item_order[blockIdx.x];
@@ -607,7 +642,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     }
 
     if (slot >= 0) {                              // a depth segment: FP32 partial state
-        float4* part = partial + (size_t)slot * (TILE * TILE);
+        float4* part = (MULTI ? view_bytes(partial, vws) : partial) + (size_t)slot * (TILE * TILE);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int lxp = (wave & 1) * 16 + (s & 1) * 8 + lx, lyp = (wave >> 1) * 16 + (s >> 1) * 8 + ly;
@@ -616,11 +651,13 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         return;
     }
     const size_t P = (size_t)W * H;
+    const size_t vp = MULTI ? (size_t)blockIdx.y * P : 0;   // first pixel of this view's images
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         if (!valid[s]) continue;
         const int X = wx0 + (s & 1) * 8 + lx, Y = wy0 + (s >> 1) * 8 + ly;
-        const size_t i = (size_t)Y * W + X;
+        const size_t i = vp + (size_t)Y * W + X;
+        const size_t ic = 2 * vp + i;             // channel 0 of out_rgb's [3][H][W] view
         // the background behind the last splat (a final blend in per-fragment mode)
         float4 v = make_float4(fmaf(T[s], bg0, C[s][0]), fmaf(T[s], bg1, C[s][1]),
                                fmaf(T[s], bg2, C[s][2]), T[s]);
@@ -629,9 +666,9 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         }
         fb_store(fb, fb_fmt, i, v);
         if (out_rgb) {
-            out_rgb[i] = v.x;
-            out_rgb[P + i] = v.y;
-            out_rgb[2 * P + i] = v.z;
+            out_rgb[ic] = v.x;
+            out_rgb[P + ic] = v.y;
+            out_rgb[2 * P + ic] = v.z;
         }
         if (out_T) out_T[i] = v.w;
         if (INSTR && out_cov) out_cov[i] = (int32_t)ncov[s];
@@ -655,7 +692,14 @@ __global__ __launch_bounds__(256) void k_raster_merge(
     int ntiles, int tiles_x, int W, int H, const int32_t* __restrict__ tile_k,
     const int32_t* __restrict__ tile_first, const float4* __restrict__ partial, float bg0,
     float bg1, float bg2, int fb_fmt, void* __restrict__ fb, float* __restrict__ out_rgb,
-    float* __restrict__ out_T) {
+    float* __restrict__ out_T, uint64_t vws) {
+    const uint64_t PV = (uint64_t)W * H;
+    tile_k = view_bytes(tile_k, vws);
+    tile_first = view_bytes(tile_first, vws);
+    partial = view_bytes(partial, vws);
+    fb = view_bytes(fb, PV * fb_bytes_per_pixel(fb_fmt));
+    out_rgb = view_at(out_rgb, 3 * PV);
+    out_T = view_at(out_T, PV);
     const int t = blockIdx.x;
     const int k = tile_k[t], f = tile_first[t];
     if (k <= 1 || f < 0 || f + k > ITEMS_PER_TILE * ntiles) return;
@@ -755,7 +799,7 @@ __device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Wa
     for (int j = 0; j < 9; ++j) tg[tid * 9 + j] = 0.f;
 }
 
-template <int RFMT, bool INSTR>
+template <int RFMT, bool INSTR, bool MULTI>
 __global__ __launch_bounds__(NT) void k_raster_bwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
     const uint2* __restrict__ rect, const int32_t* __restrict__ order,
@@ -763,9 +807,23 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     float amin, float amax, float tmin, int fb_fmt, const void* __restrict__ fb,
     const float* __restrict__ dL_dimg, const float* __restrict__ dL_dT,
     int mode, int X, float* __restrict__ grad, float* __restrict__ bgpart,
-    int32_t* __restrict__ out_live, unsigned long long* __restrict__ stats) {
+    int32_t* __restrict__ out_live, unsigned long long* __restrict__ stats, uint64_t vws) {
     __shared__ Walk w;
     __shared__ float tg[BATCH * 9];     // GS_REDUCE_TILE: per staged splat, the tile's gradient
+    if constexpr (MULTI) {
+        const uint64_t PV = (uint64_t)W * H;
+        nvis_ptr = view_at(nvis_ptr, 1);
+        rec = view_bytes(rec, vws);
+        rect = view_bytes(rect, vws);
+        order = view_bytes(order, vws);
+        bits = view_bytes(bits, vws);
+        grad = view_bytes(grad, vws);
+        bgpart = view_bytes(bgpart, vws);
+        fb = view_bytes(fb, PV * fb_bytes_per_pixel(fb_fmt));
+        dL_dimg = view_at(dL_dimg, 3 * PV);
+        dL_dT = view_at(dL_dT, PV);
+        out_live = view_at(out_live, PV);
+    }
     int tile = order[blockIdx.x];
     if ((unsigned)tile >= gridDim.x) tile = (int)blockIdx.x;   // a schedule not built for this grid
     const int tid = threadIdx.x, lane = tid & 63;
@@ -982,7 +1040,15 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
     int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
     const float* __restrict__ grad, const float* __restrict__ rgb, int saturate,
     float* __restrict__ g_m, float* __restrict__ g_c, float* __restrict__ g_o,
-    float* __restrict__ g_rgb) {
+    float* __restrict__ g_rgb, uint64_t vws) {
+    sorted_ids = view_at(sorted_ids, (uint64_t)n);
+    nvis_ptr = view_at(nvis_ptr, 1);
+    grad = view_bytes(grad, vws);
+    rgb = view_at(rgb, 3ull * n);
+    g_m = view_at(g_m, 2ull * n);
+    g_c = view_at(g_c, 3ull * n);
+    g_o = view_at(g_o, (uint64_t)n);
+    g_rgb = view_at(g_rgb, 3ull * n);
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     int nvis = *nvis_ptr;
@@ -1013,13 +1079,19 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
     g_rgb[3 * (size_t)id + 2] = v[8];
 }
 
-// dL/dbackground: the per-tile partial sums added in tile order (deterministic).
-__global__ __launch_bounds__(256) void k_bg_reduce(int ntiles, const float* __restrict__ bgpart,
+// dL/dbackground: the per-tile partial sums of every view, added in a fixed order
+// (deterministic). The background is one colour shared by the views, so its gradient is their sum.
+__global__ __launch_bounds__(256) void k_bg_reduce(int ntiles, int nviews,
+                                                   const float* __restrict__ bgpart, uint64_t vws,
                                                    float* __restrict__ out) {
     __shared__ float s[3][256];
     float a[3] = {0.f, 0.f, 0.f};
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
-        for (int c = 0; c < 3; ++c) a[c] += bgpart[(size_t)t * 4 + c];
+    for (int v = 0; v < nviews; ++v) {
+        const float* bp = reinterpret_cast<const float*>(
+            reinterpret_cast<uintptr_t>(bgpart) + (uint64_t)v * vws);
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
+            for (int c = 0; c < 3; ++c) a[c] += bp[(size_t)t * 4 + c];
+    }
     for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = a[c];
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -1096,26 +1168,29 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
 static hipError_t raster_setup(const gs_config& cfg, int width, int height, int n,
                                const int32_t* sorted_ids, const int32_t* n_visible,
                                const float* means2d, const float* conics, const float* opac,
-                               const float* rgb, const RasterWs& r, hipStream_t s) {
+                               const float* rgb, const RasterWs& r, hipStream_t s,
+                               const Views& vs) {
     const int tiles_x = (width + TILE - 1) / TILE;
     const int ntiles = tiles_of(width, height);
-    hipError_t e = launch_fill_u32(r.weights, (size_t)ntiles, 0u, s);
+    const int V = vs.count;
+    hipError_t e = launch_fill_u32(r.weights, (size_t)ntiles, 0u, s, V, vs.ws);
     if (e != hipSuccess) return e;
     if (n > 0) {
         const int sat = (cfg.fb_format == FB_UNORM16 || cfg.fb_format == FB_UNORM8) ? 1 : 0;
-        hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN), dim3(256), 0, s,
-                           n, sorted_ids, n_visible, means2d, conics, opac, rgb, width, height,
+        hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V), dim3(256), 0,
+                           s, n, sorted_ids, n_visible, means2d, conics, opac, rgb, width, height,
                            cfg.alpha_min, sat, tiles_x, ntiles, (Rec*)r.rec, (uint2*)r.rect,
-                           r.weights, r.bits, r.wpr, r.colcnt);
+                           r.weights, r.bits, r.wpr, r.colcnt, vs.ws);
     }
-    hipLaunchKernelGGL(k_plan_tiles, dim3(1), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
-                       r.split, r.tile_k, r.tile_first, r.counters);
+    hipLaunchKernelGGL(k_plan_tiles, dim3(1, V), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
+                       r.split, r.tile_k, r.tile_first, r.counters, vs.ws);
     if (r.split) {
-        hipLaunchKernelGGL(k_plan_cuts, dim3(ntiles), dim3(64), 0, s, r.weights,
+        hipLaunchKernelGGL(k_plan_cuts, dim3(ntiles, V), dim3(64), 0, s, r.weights,
                            (const uint16_t*)r.colcnt, r.wpr, ntiles, (const int32_t*)r.tile_k,
-                           (const int32_t*)r.tile_first, r.items, r.item_w);
-        hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(NBUCKETS), 0, s, (const uint32_t*)r.item_w,
-                           ntiles, (const unsigned long long*)r.counters, r.item_order);
+                           (const int32_t*)r.tile_first, r.items, r.item_w, vs.ws);
+        hipLaunchKernelGGL(k_plan_items, dim3(1, V), dim3(NBUCKETS), 0, s,
+                           (const uint32_t*)r.item_w, ntiles, (const unsigned long long*)r.counters,
+                           r.item_order, vs.ws);
     }
     return hipGetLastError();
 }
@@ -1125,38 +1200,46 @@ static bool saturating(int fmt) { return fmt == FB_UNORM16 || fmt == FB_UNORM8; 
 hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int n,
                                const int32_t* sorted_ids, const int32_t* n_visible,
                                const float* means2d, const float* conics, const float* opac,
-                               const float* rgb, void* ws, hipStream_t s) {
+                               const float* rgb, void* ws, hipStream_t s, const Views& vs) {
     const RasterWs r = carve_raster_ws(ws, n, width, height, false);
     return raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics, opac, rgb,
-                        r, s);
+                        r, s, vs);
 }
 
 using FwdKernel = void (*)(int, const int32_t*, const Rec*, const uint2*, const int32_t*,
                           const uint32_t*, int, int, int, int, int, const int4*, const int32_t*,
                           float4*, float, float, float, float, float, float, int, void*, float*,
-                          float*, int32_t*, unsigned long long*);
+                          float*, int32_t*, unsigned long long*, uint64_t);
 
-template <bool TC, bool IN>
+template <bool TC, bool IN, bool MU>
 static FwdKernel fwd_by_fmt(int rfmt) {
     switch (rfmt) {
-    case FB_F32: return k_raster_fwd<FB_F32, TC, IN>;
-    case FB_F16: return k_raster_fwd<FB_F16, TC, IN>;
-    case FB_UNORM16: return k_raster_fwd<FB_UNORM16, TC, IN>;
-    case FB_BF16: return k_raster_fwd<FB_BF16, TC, IN>;
-    case FB_UNORM8: return k_raster_fwd<FB_UNORM8, TC, IN>;
-    default: return k_raster_fwd<-1, TC, IN>;
+    case FB_F32: return k_raster_fwd<FB_F32, TC, IN, MU>;
+    case FB_F16: return k_raster_fwd<FB_F16, TC, IN, MU>;
+    case FB_UNORM16: return k_raster_fwd<FB_UNORM16, TC, IN, MU>;
+    case FB_BF16: return k_raster_fwd<FB_BF16, TC, IN, MU>;
+    case FB_UNORM8: return k_raster_fwd<FB_UNORM8, TC, IN, MU>;
+    default: return k_raster_fwd<-1, TC, IN, MU>;
     }
+}
+
+template <bool MU>
+static FwdKernel fwd_kernel(int rfmt, bool tcull, bool instr) {
+    return tcull ? (instr ? fwd_by_fmt<true, true, MU>(rfmt) : fwd_by_fmt<true, false, MU>(rfmt))
+                 : (instr ? fwd_by_fmt<false, true, MU>(rfmt) : fwd_by_fmt<false, false, MU>(rfmt));
 }
 
 hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                              const int32_t* sorted_ids, const int32_t* n_visible,
                              const float* means2d, const float* conics, const float* opac,
                              const float* rgb, void* fb, float* out_rgb, float* out_T,
-                             int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s) {
+                             int32_t* out_cov, gs_stats* stats, void* ws, hipStream_t s,
+                             const Views& vs) {
     const RasterWs r = carve_raster_ws(ws, n, width, height, false);
+    const int V = vs.count;
     if (!(cfg.flags & GS_FLAG_REUSE_SETUP)) {
         hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
-                                     opac, rgb, r, s);
+                                     opac, rgb, r, s, vs);
         if (e0 != hipSuccess) return e0;
     }
     const int tiles_x = (width + TILE - 1) / TILE;
@@ -1166,9 +1249,8 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_cov;
     // the depth split needs the at-rest state, no T-culling and no per-pixel counters
     const bool split = r.split && rfmt < 0 && !tcull && !instr;
-    FwdKernel k = tcull ? (instr ? fwd_by_fmt<true, true>(rfmt) : fwd_by_fmt<true, false>(rfmt))
-                        : (instr ? fwd_by_fmt<false, true>(rfmt) : fwd_by_fmt<false, false>(rfmt));
-    hipLaunchKernelGGL(k, dim3(split ? ITEMS_PER_TILE * ntiles : ntiles), dim3(NT), 0, s, n,
+    FwdKernel k = V > 1 ? fwd_kernel<true>(rfmt, tcull, instr) : fwd_kernel<false>(rfmt, tcull, instr);
+    hipLaunchKernelGGL(k, dim3(split ? ITEMS_PER_TILE * ntiles : ntiles, V), dim3(NT), 0, s, n,
                        n_visible,
                        (const Rec*)r.rec, (const uint2*)r.rect, (const int32_t*)r.order,
                        (const uint32_t*)r.bits, r.wpr, width, height, tiles_x, ntiles,
@@ -1177,13 +1259,14 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                        cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.background[0],
                        cfg.background[1], cfg.background[2], cfg.fb_format, fb, out_rgb, out_T,
                        out_cov,
-                       (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
+                       (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr,
+                       vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !split) return e;
-    hipLaunchKernelGGL(k_raster_merge, dim3(ntiles), dim3(256), 0, s, ntiles, tiles_x, width, height,
-                       (const int32_t*)r.tile_k, (const int32_t*)r.tile_first,
+    hipLaunchKernelGGL(k_raster_merge, dim3(ntiles, V), dim3(256), 0, s, ntiles, tiles_x, width,
+                       height, (const int32_t*)r.tile_k, (const int32_t*)r.tile_first,
                        (const float4*)r.partial, cfg.background[0], cfg.background[1],
-                       cfg.background[2], cfg.fb_format, fb, out_rgb, out_T);
+                       cfg.background[2], cfg.fb_format, fb, out_rgb, out_T, vs.ws);
     return hipGetLastError();
 }
 
@@ -1192,16 +1275,18 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                              const float* means2d, const float* conics, const float* opac,
                              const float* rgb, const void* fb, const float* dL_dimg,
                              float* g_means2d, float* g_conics, float* g_opac, float* g_rgb, const float* dL_dT, float* dL_dbg,
-                             int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s) {
+                             int32_t* out_live, gs_stats* stats, void* ws, hipStream_t s,
+                             const Views& vs) {
     const RasterWs r = carve_raster_ws(ws, n, width, height, true);
     const int sat = (int)saturating(cfg.fb_format);
+    const int V = vs.count;
     if (n > 0) {
-        hipError_t e = launch_fill_u32(r.grad, (size_t)n * GRAD_STRIDE, 0u, s);
+        hipError_t e = launch_fill_u32(r.grad, (size_t)n * GRAD_STRIDE, 0u, s, V, vs.ws);
         if (e != hipSuccess) return e;
     }
     if (!(cfg.flags & GS_FLAG_REUSE_SETUP)) {
         hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
-                                     opac, rgb, r, s);
+                                     opac, rgb, r, s, vs);
         if (e0 != hipSuccess) return e0;
     }
     const int tiles_x = (width + TILE - 1) / TILE;
@@ -1210,36 +1295,41 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_live;
     void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
               int, int, int, float, float, float, int, const void*, const float*, const float*, int,
-              int, float*, float*, int32_t*, unsigned long long*) = nullptr;
-#define GSR_BWD_PICK(IN)                                             \
-    switch (rfmt) {                                                  \
-    case FB_F32: k = k_raster_bwd<FB_F32, IN>; break;                \
-    case FB_F16: k = k_raster_bwd<FB_F16, IN>; break;                \
-    case FB_UNORM16: k = k_raster_bwd<FB_UNORM16, IN>; break;        \
-    case FB_BF16: k = k_raster_bwd<FB_BF16, IN>; break;              \
-    case FB_UNORM8: k = k_raster_bwd<FB_UNORM8, IN>; break;          \
-    default: k = k_raster_bwd<-1, IN>; break;                        \
+              int, float*, float*, int32_t*, unsigned long long*, uint64_t) = nullptr;
+#define GSR_BWD_PICK(IN, MU)                                             \
+    switch (rfmt) {                                                      \
+    case FB_F32: k = k_raster_bwd<FB_F32, IN, MU>; break;                \
+    case FB_F16: k = k_raster_bwd<FB_F16, IN, MU>; break;                \
+    case FB_UNORM16: k = k_raster_bwd<FB_UNORM16, IN, MU>; break;        \
+    case FB_BF16: k = k_raster_bwd<FB_BF16, IN, MU>; break;              \
+    case FB_UNORM8: k = k_raster_bwd<FB_UNORM8, IN, MU>; break;          \
+    default: k = k_raster_bwd<-1, IN, MU>; break;                        \
     }
-    if (instr) { GSR_BWD_PICK(true) } else { GSR_BWD_PICK(false) }
+    if (V > 1) {
+        if (instr) { GSR_BWD_PICK(true, true) } else { GSR_BWD_PICK(false, true) }
+    } else {
+        if (instr) { GSR_BWD_PICK(true, false) } else { GSR_BWD_PICK(false, false) }
+    }
 #undef GSR_BWD_PICK
-    hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
+    hipLaunchKernelGGL(k, dim3(nblocks, V), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
                        (const uint2*)r.rect, (const int32_t*)r.order, (const uint32_t*)r.bits,
                        r.wpr, width, height, tiles_x,
                        cfg.alpha_min, cfg.alpha_max, cfg.t_min_bwd, cfg.fb_format, fb, dL_dimg,
                        dL_dT, cfg.reduce_mode, cfg.reduce_threshold, r.grad,
                        dL_dbg ? r.bgpart : nullptr, out_live,
-                       (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr);
+                       (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr,
+                       vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dL_dbg) {
-        hipLaunchKernelGGL(k_bg_reduce, dim3(1), dim3(256), 0, s, nblocks, (const float*)r.bgpart,
-                           dL_dbg);
+        hipLaunchKernelGGL(k_bg_reduce, dim3(1), dim3(256), 0, s, nblocks, V,
+                           (const float*)r.bgpart, vs.ws, dL_dbg);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256), dim3(256), 0, s, n, sorted_ids,
-                       n_visible, r.grad, rgb, sat, g_means2d, g_conics, g_opac, g_rgb);
+    hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256, V), dim3(256), 0, s, n, sorted_ids,
+                       n_visible, r.grad, rgb, sat, g_means2d, g_conics, g_opac, g_rgb, vs.ws);
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 // digit-major [digit][block] table, (3) a stable scatter in which every block ranks its keys
 // round by round (256 keys per round, one per thread, in input order), ranking equal digits
 // inside a wave with eight ballots and across the four waves through LDS counts.
+// Several views sort in one launch per step (grid y = view): each view's keys, ids and count are
+// its part of [V][n] arrays, and its histograms and ping-pong buffers live in its workspace slab.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -20,12 +22,23 @@ __device__ __forceinline__ int dev_count(const int32_t* n_dev, int n_max) {
     return n < 0 ? 0 : (n > n_max ? n_max : n);
 }
 
+// A sort buffer of a view: the caller's [V][n] array (in_ws = 0) or the view's workspace slab.
+template <typename T>
+__device__ __forceinline__ T* sort_buf(T* p, int in_ws, int n_max, uint64_t vws) {
+    return in_ws ? view_bytes(p, vws) : view_at(p, (uint64_t)n_max);
+}
+
 template <typename K>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const K* __restrict__ keys, int n_max,
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const K* __restrict__ keys, int in_ws,
+                                                            int n_max,
                                                             const int32_t* __restrict__ n_dev,
                                                             int shift, int nblocks,
-                                                            uint32_t* __restrict__ hist) {
+                                                            uint32_t* __restrict__ hist,
+                                                            uint64_t vws) {
     __shared__ uint32_t h[256];
+    keys = sort_buf(keys, in_ws, n_max, vws);
+    n_dev = view_at(n_dev, 1);
+    hist = view_bytes(hist, vws);
     const int tid = threadIdx.x;
     h[tid] = 0;
     __syncthreads();
@@ -42,9 +55,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const K* __restrict_
 }
 
 // Exclusive scan of `count` uint32 in three launches: block sums, scan of the sums, apply.
+// Batched over views: `in`, `out` and `sums` of view v are `vws` bytes after view v - 1's.
 __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ in, size_t count,
-                                                   uint32_t* __restrict__ sums) {
+                                                   uint32_t* __restrict__ sums, uint64_t vws) {
     __shared__ uint32_t red[4];
+    in = view_bytes(in, vws);
+    sums = view_bytes(sums, vws);
     const size_t base = (size_t)blockIdx.x * SCAN_ITEMS;
     uint32_t s = 0;
     for (int j = 0; j < SCAN_ITEMS / 256; ++j) {
@@ -58,8 +74,10 @@ __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ 
 }
 
 // Single block: exclusive scan of `count` (<= 1024 * 64) block sums in place.
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, int count) {
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, int count,
+                                                   uint64_t vws) {
     __shared__ uint32_t part[1024];
+    sums = view_bytes(sums, vws);
     const int per = (count + 1023) / 1024;
     const int lo = threadIdx.x * per;
     uint32_t s = 0;
@@ -84,9 +102,12 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, 
 
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, size_t count,
                                                     const uint32_t* __restrict__ sums,
-                                                    uint32_t* __restrict__ out) {
+                                                    uint32_t* __restrict__ out, uint64_t vws) {
     // each thread owns 16 consecutive entries of the block's 4096
     __shared__ uint32_t part[256];
+    in = view_bytes(in, vws);
+    sums = view_bytes(sums, vws);
+    out = view_bytes(out, vws);
     const size_t base = (size_t)blockIdx.x * SCAN_ITEMS + (size_t)threadIdx.x * 16;
     uint32_t v[16];
     uint32_t s = 0;
@@ -111,22 +132,30 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 }
 
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t count, uint32_t* sums,
-                                 hipStream_t s) {
+                                 hipStream_t s, const Views& vs) {
     if (count == 0) return hipSuccess;
     const int blocks = (int)((count + SCAN_ITEMS - 1) / SCAN_ITEMS);
-    hipLaunchKernelGGL(k_scan_sums, dim3(blocks), dim3(256), 0, s, in, count, sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, blocks);
-    hipLaunchKernelGGL(k_scan_apply, dim3(blocks), dim3(256), 0, s, in, count, sums, out);
+    const int V = vs.count;
+    hipLaunchKernelGGL(k_scan_sums, dim3(blocks, V), dim3(256), 0, s, in, count, sums, vs.ws);
+    hipLaunchKernelGGL(k_scan_top, dim3(1, V), dim3(1024), 0, s, sums, blocks, vs.ws);
+    hipLaunchKernelGGL(k_scan_apply, dim3(blocks, V), dim3(256), 0, s, in, count, sums, out,
+                       vs.ws);
     return hipGetLastError();
 }
 
 template <typename K>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
-    const K* __restrict__ kin, const int32_t* __restrict__ vin, K* __restrict__ kout,
-    int32_t* __restrict__ vout, int n_max, const int32_t* __restrict__ n_dev, int shift,
-    int nblocks, const uint32_t* __restrict__ offsets) {
+    const K* __restrict__ kin, const int32_t* __restrict__ vin, int in_ws, K* __restrict__ kout,
+    int32_t* __restrict__ vout, int out_ws, int n_max, const int32_t* __restrict__ n_dev,
+    int shift, int nblocks, const uint32_t* __restrict__ offsets, uint64_t vws) {
     __shared__ uint32_t s_off[256];
     __shared__ uint16_t s_cnt[2][4][256];
+    kin = sort_buf(kin, in_ws, n_max, vws);
+    vin = sort_buf(vin, in_ws, n_max, vws);
+    kout = sort_buf(kout, out_ws, n_max, vws);
+    vout = sort_buf(vout, out_ws, n_max, vws);
+    n_dev = view_at(n_dev, 1);
+    offsets = view_bytes(offsets, vws);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = dev_count(n_dev, n_max);
     const int start = blockIdx.x * SORT_ITEMS;
@@ -175,7 +204,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
 template <typename K>
 __global__ void k_copy_pairs(const K* __restrict__ ks, const int32_t* __restrict__ vs,
                              K* __restrict__ kd, int32_t* __restrict__ vd, int n_max,
-                             const int32_t* __restrict__ n_dev) {
+                             const int32_t* __restrict__ n_dev, uint64_t vws) {
+    ks = view_bytes(ks, vws);          // the workspace's ping-pong buffers
+    vs = view_bytes(vs, vws);
+    kd = view_at(kd, (uint64_t)n_max);
+    vd = view_at(vd, (uint64_t)n_max);
+    n_dev = view_at(n_dev, 1);
     const int n = dev_count(n_dev, n_max);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         kd[i] = ks[i];
@@ -188,8 +222,11 @@ __global__ void k_copy_pairs(const K* __restrict__ ks, const int32_t* __restrict
 // first in id order, then the culled ones in id order; n_visible = number of visible splats.
 
 __global__ __launch_bounds__(SORT_THREADS) void k_compact_count(const uint32_t* __restrict__ kid,
-                                                                int n, uint32_t* __restrict__ cnt) {
+                                                                int n, uint32_t* __restrict__ cnt,
+                                                                uint64_t vws) {
     __shared__ uint32_t red[4];
+    kid = view_bytes(kid, vws);
+    cnt = view_bytes(cnt, vws);
     const int start = blockIdx.x * SORT_ITEMS;
     uint32_t c = 0;
     for (int r = 0; r < SORT_ROUNDS; ++r) {
@@ -204,8 +241,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact_count(const uint32_t* 
 __global__ __launch_bounds__(SORT_THREADS) void k_compact_scatter(
     const uint32_t* __restrict__ kid, int n, int nblocks, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ offs, uint32_t* __restrict__ keys, int32_t* __restrict__ ids,
-    int32_t* __restrict__ n_visible) {
+    int32_t* __restrict__ n_visible, uint64_t vws) {
     __shared__ uint32_t s_w[2][4];
+    kid = view_bytes(kid, vws);
+    cnt = view_bytes(cnt, vws);
+    offs = view_bytes(offs, vws);
+    keys = view_at(keys, (uint64_t)n);
+    ids = view_at(ids, (uint64_t)n);
+    n_visible = view_at(n_visible, 1);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = offs[nblocks - 1] + cnt[nblocks - 1];
     if (blockIdx.x == 0 && tid == 0) *n_visible = (int32_t)total;
@@ -237,18 +280,19 @@ size_t compact_ws_bytes(int n) {
 }
 
 hipError_t launch_compact(int n, const uint32_t* key_by_id, uint32_t* keys, int32_t* ids,
-                          int32_t* n_visible, void* ws, hipStream_t s) {
-    if (n == 0) return launch_fill_u32(n_visible, 1, 0u, s);
+                          int32_t* n_visible, void* ws, hipStream_t s, const Views& vs) {
+    if (n == 0) return launch_fill_u32(n_visible, (size_t)vs.count, 0u, s);
     const int nb = (n + SORT_ITEMS - 1) / SORT_ITEMS;
     char* p = (char*)ws;
     uint32_t* cnt = (uint32_t*)p;  p += align_up((size_t)(nb + 1) * 4);
     uint32_t* offs = (uint32_t*)p; p += align_up((size_t)(nb + 1) * 4);
     uint32_t* sums = (uint32_t*)p;
-    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(SORT_THREADS), 0, s, key_by_id, n, cnt);
-    hipError_t e = launch_exclusive_scan(cnt, offs, (size_t)nb, sums, s);
+    hipLaunchKernelGGL(k_compact_count, dim3(nb, vs.count), dim3(SORT_THREADS), 0, s, key_by_id,
+                       n, cnt, vs.ws);
+    hipError_t e = launch_exclusive_scan(cnt, offs, (size_t)nb, sums, s, vs);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(SORT_THREADS), 0, s, key_by_id, n, nb,
-                       cnt, offs, keys, ids, n_visible);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nb, vs.count), dim3(SORT_THREADS), 0, s, key_by_id,
+                       n, nb, cnt, offs, keys, ids, n_visible, vs.ws);
     return hipGetLastError();
 }
 
@@ -264,8 +308,9 @@ size_t sort_ws_bytes(int n, int key_bytes) {
 
 template <typename K>
 static hipError_t sort_pairs(int n, K* keys, int32_t* vals, const int32_t* n_dev, int end_bit,
-                             void* ws, hipStream_t s) {
+                             void* ws, hipStream_t s, const Views& vs) {
     if (n == 0) return hipSuccess;
+    const int V = vs.count;
     const int nb = sort_blocks(n);
     const size_t table = 256 * (size_t)nb;
     char* p = (char*)ws;
@@ -277,34 +322,36 @@ static hipError_t sort_pairs(int n, K* keys, int32_t* vals, const int32_t* n_dev
     if ((table + SCAN_ITEMS - 1) / SCAN_ITEMS > 1024 * 64) return hipErrorInvalidValue;
     K* kin = keys; int32_t* vin = vals;
     K* kout = kalt; int32_t* vout = valt;
+    int in_ws = 0, out_ws = 1;
     int passes = 0;
     for (int shift = 0; shift < end_bit; shift += 8, ++passes) {
-        hipLaunchKernelGGL(k_sort_hist<K>, dim3(nb), dim3(SORT_THREADS), 0, s, kin, n, n_dev,
-                           shift, nb, hist);
-        hipError_t e = launch_exclusive_scan(hist, offs, table, sums, s);
+        hipLaunchKernelGGL(k_sort_hist<K>, dim3(nb, V), dim3(SORT_THREADS), 0, s, kin, in_ws, n,
+                           n_dev, shift, nb, hist, vs.ws);
+        hipError_t e = launch_exclusive_scan(hist, offs, table, sums, s, vs);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sort_scatter<K>, dim3(nb), dim3(SORT_THREADS), 0, s, kin, vin, kout,
-                           vout, n, n_dev, shift, nb, offs);
+        hipLaunchKernelGGL(k_sort_scatter<K>, dim3(nb, V), dim3(SORT_THREADS), 0, s, kin, vin,
+                           in_ws, kout, vout, out_ws, n, n_dev, shift, nb, offs, vs.ws);
         K* tk = kin; kin = kout; kout = tk;
         int32_t* tv = vin; vin = vout; vout = tv;
+        const int tw = in_ws; in_ws = out_ws; out_ws = tw;
     }
     if (passes & 1) {   // result sits in the alternate buffers: copy back
         int blocks = (n + 255) / 256;
         if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(k_copy_pairs<K>, dim3(blocks), dim3(256), 0, s, kin, vin, keys, vals,
-                           n, n_dev);
+        hipLaunchKernelGGL(k_copy_pairs<K>, dim3(blocks, V), dim3(256), 0, s, kin, vin, keys,
+                           vals, n, n_dev, vs.ws);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_sort_u32(int n, uint32_t* keys, int32_t* vals, const int32_t* n_dev, void* ws,
-                           hipStream_t s) {
-    return sort_pairs<uint32_t>(n, keys, vals, n_dev, 32, ws, s);
+                           hipStream_t s, const Views& vs) {
+    return sort_pairs<uint32_t>(n, keys, vals, n_dev, 32, ws, s, vs);
 }
 
 hipError_t launch_sort_u64(int n, uint64_t* keys, int32_t* vals, const int32_t* n_dev,
                            int end_bit, void* ws, hipStream_t s) {
-    return sort_pairs<uint64_t>(n, keys, vals, n_dev, end_bit, ws, s);
+    return sort_pairs<uint64_t>(n, keys, vals, n_dev, end_bit, ws, s, one_view());
 }
 
 }  // namespace gsr

@@ -2,7 +2,9 @@
 autograd Functions.
 
 PyTorch only supplies device memory and the current stream; every step of the method runs in the
-HIP library. The forward state kept for the backward is O(N) splat records plus the O(W H)
+HIP library. Passing a list of cameras renders those views of one scene in the same launches
+(the library's view batching): per-view tensors then carry a leading view dimension, and the
+backward sums the views' gradients w.r.t. the shared 3D parameters. The forward state kept for the backward is O(N) splat records plus the O(W H)
 framebuffer: nothing per fragment is stored, the backward rematerialises each fragment from the
 framebuffer state (Procedure 1).
 """
@@ -38,7 +40,7 @@ class RasterConfig:
     stats: bool = False
     background: tuple = (0.0, 0.0, 0.0)   # C += T_final background (zero: Eq. 2 as printed)
 
-    def c(self) -> L.GsConfig:
+    def c(self, n_views: int = 1) -> L.GsConfig:
         c = L.GsConfig()
         c.alpha_min = self.alpha_min
         c.alpha_max = self.alpha_max
@@ -53,7 +55,22 @@ class RasterConfig:
         c.flags = 1 if self.stats else 0
         for k in range(3):
             c.background[k] = float(self.background[k])
+        c.n_views = int(n_views)
         return c
+
+
+def is_views(cam) -> bool:
+    """A list or tuple of cameras (several views per call) rather than one camera."""
+    return isinstance(cam, (list, tuple))
+
+
+def cameras_c(cam):
+    """(gs_camera or an array of them, number of views) for one camera or a list of cameras."""
+    if is_views(cam):
+        if not 1 <= len(cam) <= L.MAX_VIEWS:
+            raise ValueError(f"1..{L.MAX_VIEWS} views per call, got {len(cam)}")
+        return L.camera_array([camera_c(c) for c in cam]), len(cam)
+    return camera_c(cam), 1
 
 
 def camera_c(cam) -> L.GsCamera:
@@ -117,7 +134,8 @@ def _ws_args(ws: Workspace, need: int):
 @dataclasses.dataclass
 class Projected:
     """Splats in screen space plus the depth-sorted (keys, ids) and the device-side count of
-    visible splats."""
+    visible splats. For V views of one scene every per-view tensor has a leading dimension V
+    (means2d [V,n,2], keys [V,n], n_visible [V], ...); opacities stay [n]."""
     means2d: torch.Tensor
     conics: torch.Tensor
     rgb: torch.Tensor
@@ -131,7 +149,15 @@ class Projected:
 
     @property
     def n(self) -> int:
-        return int(self.means2d.shape[0])
+        return int(self.means2d.shape[-2])
+
+    @property
+    def n_views(self) -> int:
+        return 1 if self.means2d.dim() == 2 else int(self.means2d.shape[0])
+
+    def lead(self):
+        """Leading shape of per-view tensors: () for one view, (V,) for several."""
+        return () if self.means2d.dim() == 2 else (self.n_views,)
 
 
 def _c32(t):
@@ -141,21 +167,26 @@ def _c32(t):
 
 def project(means3d, scales, quats, opacities, sh, cam, cfg: RasterConfig, ws: Workspace,
             sort: bool = True) -> Projected:
-    """gs_preprocess (projection, SH colour, culling, keys) then gs_sort."""
+    """gs_preprocess (projection, SH colour, culling, keys) then gs_sort. cam: one camera, or a
+    list of cameras of equal image size (one batched call; outputs [V, n, ..])."""
     dev = means3d.device
     n = int(means3d.shape[0])
-    cc, cm = cfg.c(), camera_c(cam)
+    cm, V = cameras_c(cam)
+    cc = cfg.c(V)
+    lead = (V,) if is_views(cam) else ()
     means3d, scales, quats, opacities, sh = map(_c32, (means3d, scales, quats, opacities, sh))
-    out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
-               rgb=torch.empty(n, 3, device=dev), depth=torch.empty(n, device=dev),
-               keys=torch.empty(n, dtype=torch.int32, device=dev),
-               ids=torch.empty(n, dtype=torch.int32, device=dev),
-               n_visible=torch.zeros(1, dtype=torch.int32, device=dev))
-    b, nb = _ws_args(ws, max(L.gs_workspace_size("preprocess", n, cm.width, cm.height, cc), 256))
+    out = dict(means2d=torch.empty(*lead, n, 2, device=dev),
+               conics=torch.empty(*lead, n, 3, device=dev),
+               rgb=torch.empty(*lead, n, 3, device=dev), depth=torch.empty(*lead, n, device=dev),
+               keys=torch.empty(*lead, n, dtype=torch.int32, device=dev),
+               ids=torch.empty(*lead, n, dtype=torch.int32, device=dev),
+               n_visible=torch.zeros(V, dtype=torch.int32, device=dev))
+    cm0 = cm[0] if is_views(cam) else cm
+    b, nb = _ws_args(ws, max(L.gs_workspace_size("preprocess", n, cm0.width, cm0.height, cc), 256))
     L.gs_preprocess(cm, cc, n, means3d, scales, quats, opacities, sh, out["means2d"],
                     out["conics"], out["rgb"], out["depth"], out["keys"], out["ids"],
                     out["n_visible"], b, nb, _stream(dev))
-    p = Projected(opacities=opacities, width=cm.width, height=cm.height, **out)
+    p = Projected(opacities=opacities, width=cm0.width, height=cm0.height, **out)
     if sort:
         sort_(p, ws)
     return p
@@ -182,10 +213,16 @@ def prepare_2d(means2d, conics, opacities, rgb, depth, width, height, cfg: Raste
 
 
 def sort_(p: Projected, ws: Workspace):
-    """gs_sort: stable depth sort of the visible prefix of (keys, ids), in place."""
-    n = p.n
-    b, nb = _ws_args(ws, L.gs_workspace_size("sort", n, p.width, p.height, L.GsConfig()))
-    L.gs_sort(n, p.keys, p.ids, p.n_visible, b, nb, _stream(p.keys.device))
+    """gs_sort (gs_sort_views for several views): stable depth sort of the visible prefix of
+    (keys, ids), in place."""
+    n, V = p.n, p.n_views
+    cc = L.GsConfig()
+    cc.n_views = V
+    b, nb = _ws_args(ws, L.gs_workspace_size("sort", n, p.width, p.height, cc))
+    if p.lead():
+        L.gs_sort_views(V, n, p.keys, p.ids, p.n_visible, b, nb, _stream(p.keys.device))
+    else:
+        L.gs_sort(n, p.keys, p.ids, p.n_visible, b, nb, _stream(p.keys.device))
 
 
 def new_stats(device):
@@ -207,7 +244,7 @@ def raster_setup(p: Projected, cfg: RasterConfig, ws: Workspace):
     workspace is sized for the backward here, so those calls never regrow (and lose) it."""
     dev = p.means2d.device
     W, H, n = p.width, p.height, p.n
-    cc, cm = cfg.c(), image_camera(W, H)
+    cc, cm = cfg.c(p.n_views), image_camera(W, H)
     b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc))
     L.gs_raster_setup(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, b, nb,
                       _stream(dev))
@@ -215,20 +252,23 @@ def raster_setup(p: Projected, cfg: RasterConfig, ws: Workspace):
 
 def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, image=None, T=None,
                    coverage=False, stats=None, reuse_setup=False):
-    """gs_raster_fwd: returns dict(fb, image [3,H,W], T [H,W], coverage [H,W] or None).
+    """gs_raster_fwd: returns dict(fb, image [3,H,W], T [H,W], coverage [H,W] or None), each with
+    a leading view dimension for several views.
     reuse_setup: the workspace holds raster_setup's output for exactly these inputs."""
     dev = p.means2d.device
     W, H, n = p.width, p.height, p.n
-    cc, cm = cfg.c(), image_camera(W, H)
+    lead = p.lead()
+    cc, cm = cfg.c(p.n_views), image_camera(W, H)
     if reuse_setup:
         cc.flags |= 2
     if fb is None:
-        fb = torch.empty(L.gs_framebuffer_size(W, H, cfg.fb_format), dtype=torch.uint8, device=dev)
+        fb = torch.empty(*lead, L.gs_framebuffer_size(W, H, cfg.fb_format), dtype=torch.uint8,
+                         device=dev)
     if image is None:
-        image = torch.empty(3, H, W, device=dev)
+        image = torch.empty(*lead, 3, H, W, device=dev)
     if T is None:
-        T = torch.empty(H, W, device=dev)
-    cov = torch.empty(H, W, dtype=torch.int32, device=dev) if coverage else None
+        T = torch.empty(*lead, H, W, device=dev)
+    cov = torch.empty(*lead, H, W, dtype=torch.int32, device=dev) if coverage else None
     if stats is not None:
         cc.flags |= 1
     b, nb = _ws_args(ws, L.gs_workspace_size("raster_fwd", n, W, H, cc))
@@ -241,18 +281,22 @@ def raster_backward(p: Projected, fb, dL_dimage, cfg: RasterConfig, ws: Workspac
                     stats=None, out=None, reuse_setup=False, dL_dT=None):
     """gs_raster_bwd: gradients w.r.t. (means2d, conics, opacities, rgb) by splat id and w.r.t.
     the background ('background' [3]); dL_dT [H, W] is an optional gradient of the final T.
+    For several views the 2D gradients are per view ([V, n, ..]) and the background's is their sum.
     reuse_setup: the workspace holds raster_setup's output for exactly these inputs."""
     dev = p.means2d.device
     W, H, n = p.width, p.height, p.n
-    cc, cm = cfg.c(), image_camera(W, H)
+    lead = p.lead()
+    cc, cm = cfg.c(p.n_views), image_camera(W, H)
     if reuse_setup:
         cc.flags |= 2
     if out is None:
-        out = dict(means2d=torch.empty(n, 2, device=dev), conics=torch.empty(n, 3, device=dev),
-                   opacities=torch.empty(n, device=dev), rgb=torch.empty(n, 3, device=dev))
+        out = dict(means2d=torch.empty(*lead, n, 2, device=dev),
+                   conics=torch.empty(*lead, n, 3, device=dev),
+                   opacities=torch.empty(*lead, n, device=dev),
+                   rgb=torch.empty(*lead, n, 3, device=dev))
     if "background" not in out:
         out["background"] = torch.empty(3, device=dev)
-    lv = torch.empty(H, W, dtype=torch.int32, device=dev) if live else None
+    lv = torch.empty(*lead, H, W, dtype=torch.int32, device=dev) if live else None
     if stats is not None:
         cc.flags |= 1
     b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc))
@@ -266,10 +310,12 @@ def raster_backward(p: Projected, fb, dL_dimage, cfg: RasterConfig, ws: Workspac
 
 def project_backward(means3d, scales, quats, opacities, sh, cam, cfg: RasterConfig, g2d: dict,
                      out=None):
-    """gs_preprocess_bwd: gradients w.r.t. the 3D Gaussian parameters."""
+    """gs_preprocess_bwd: gradients w.r.t. the 3D Gaussian parameters; for a list of cameras, the
+    sum over the views of g2d's [V, n, ..] gradients (accumulated on the device in view order)."""
     dev = means3d.device
     n = int(means3d.shape[0])
-    cc, cm = cfg.c(), camera_c(cam)
+    cm, V = cameras_c(cam)
+    cc = cfg.c(V)
     if out is None:
         out = dict(means3d=torch.empty_like(means3d), scales=torch.empty_like(scales),
                    quats=torch.empty_like(quats), opacities=torch.empty_like(opacities),
@@ -287,7 +333,9 @@ class GaussianRasterizeFn(torch.autograd.Function):
     """image, T = f(means3d, scales, quats, opacities, sh): projection, depth sort, ordered
     compositing (over cfg.background); the backward runs Procedures 1-2 and the projection's
     backward. Activations (exp of log-scales, sigmoid of logits) stay in torch, outside this
-    function. A loss on the final T (e.g. an alpha mask) reaches the splats through dL/dT."""
+    function. A loss on the final T (e.g. an alpha mask) reaches the splats through dL/dT.
+    With a list of cameras the views render in the same launches (image [V,3,H,W], T [V,H,W])
+    and the backward returns the sum of the views' gradients."""
 
     @staticmethod
     def forward(ctx, means3d, scales, quats, opacities, sh, cam, cfg, ws):
@@ -302,7 +350,8 @@ class GaussianRasterizeFn(torch.autograd.Function):
     def backward(ctx, d_image, d_T):
         means3d, scales, quats, opacities, sh, fb = ctx.saved_tensors
         if d_image is None:
-            d_image = torch.zeros(3, ctx.proj.height, ctx.proj.width, device=fb.device)
+            d_image = torch.zeros(*ctx.proj.lead(), 3, ctx.proj.height, ctx.proj.width,
+                                  device=fb.device)
         g2 = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws, dL_dT=d_T)
         g3 = project_backward(means3d, scales, quats, opacities, sh, ctx.cam, ctx.cfg, g2)
         return g3["means3d"], g3["scales"], g3["quats"], g3["opacities"], g3["sh"], None, None, None

@@ -1,5 +1,6 @@
-"""Fitting loop over the differentiable rasterizer: Adam on raw Gaussian parameters, one view per
-step, L2 photometric loss against target images.
+"""Fitting loop over the differentiable rasterizer: Adam on raw Gaussian parameters, one or more
+views per step (several views render in the same launches and their gradients are summed on the
+device), L2 photometric loss against target images.
 
 Parameters are kept raw (means, log-scales, quaternions, opacity logits, SH) and activated in
 torch (exp, sigmoid; the projection normalises quaternions), then rendered with
@@ -7,7 +8,7 @@ GaussianRasterizeFn; the rasterizer's forward state is rematerialised in its bac
 only per-view memory beyond the parameters is the framebuffer and the O(N) splat records.
 
 Run as a module for the 500k-Gaussian, 8-camera, 1280x720 fitting workload:
-    python -m paper_2505_18764_amd.train [--steps 300] [--n 500000]
+    python -m paper_2505_18764_amd.train [--steps 300] [--n 500000] [--views-per-step 1]
 """
 from __future__ import annotations
 
@@ -45,16 +46,25 @@ def render(params: GaussianParams, cam, cfg: RasterConfig, ws: Workspace):
 
 
 def fit(params: GaussianParams, cams, targets, steps: int, lr: float = 1e-3, cfg=None,
-        log_every: int = 10, callback=None):
-    """Adam (torch defaults, lr) on all raw parameters; view k % len(cams) at step k."""
+        log_every: int = 10, callback=None, views_per_step: int = 1):
+    """Adam (torch defaults, lr) on all raw parameters. Step k renders views
+    (k B + j) % len(cams), j < B = views_per_step, in one batched call (B > 1) and takes the mean
+    squared error over them."""
     cfg = cfg or RasterConfig(sh_degree=params.sh_degree)
     ws = Workspace(params.means.device)
     opt = torch.optim.Adam(params.parameters(), lr=lr)
     hist = []
+    B = views_per_step
+    tgt = torch.stack(list(targets)) if B > 1 else None
     for k in range(steps):
-        v = k % len(cams)
-        img, _ = render(params, cams[v], cfg, ws)
-        loss = torch.mean((img - targets[v]) ** 2)
+        if B > 1:
+            vs = [(k * B + j) % len(cams) for j in range(B)]
+            img, _ = render(params, [cams[v] for v in vs], cfg, ws)
+            loss = torch.mean((img - tgt[vs]) ** 2)
+        else:
+            v = k % len(cams)
+            img, _ = render(params, cams[v], cfg, ws)
+            loss = torch.mean((img - targets[v]) ** 2)
         opt.zero_grad(set_to_none=True)
         loss.backward()
         opt.step()
@@ -74,6 +84,7 @@ def main():
     ap.add_argument("--width", type=int, default=c["width"])
     ap.add_argument("--height", type=int, default=c["height"])
     ap.add_argument("--fb-format", default="f16")
+    ap.add_argument("--views-per-step", type=int, default=1)
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     fx = c["fx"] * args.width / c["width"]
@@ -93,10 +104,12 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = fit(params, cams, targets, args.steps, lr=c["lr"], cfg=cfg,
-               callback=lambda k, l: print(f"step {k} loss {l:.6f}", flush=True))
+               callback=lambda k, l: print(f"step {k} loss {l:.6f}", flush=True),
+               views_per_step=args.views_per_step)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(json.dumps({"steps": args.steps, "n": args.n, "resolution": [args.width, args.height],
+                      "views_per_step": args.views_per_step,
                       "s_per_step": dt / args.steps, "loss_first": hist[0][1],
                       "loss_last": hist[-1][1], "history": hist}))
 

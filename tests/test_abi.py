@@ -122,3 +122,49 @@ def test_invalid_arguments_rejected_on_host():
     cz.znear = 0.0
     assert L.lib().gs_preprocess_bwd(ctypes.byref(cz), ctypes.byref(cfg), 0, *([None] * 14),
                                      None) == 1
+
+
+def test_view_batches_checked_on_host():
+    """Several views per call: the view count, the cameras' common image size, the per-view
+    workspace slabs and the entry points that take one view only are checked before any launch."""
+    from paper_2505_18764_amd import _lib as L
+    c1 = L.gs_config_default()
+    for V in (2, 5, 16):
+        cv = L.gs_config_default()
+        cv.n_views = V
+        for op in ("preprocess", "sort", "raster_fwd", "raster_bwd", "all"):
+            one = L.gs_workspace_size(op, 12_345, 640, 480, c1)
+            assert L.gs_workspace_size(op, 12_345, 640, 480, cv) == V * ((one + 255) // 256 * 256)
+    cv = L.gs_config_default()
+    cv.n_views = 17
+    assert L.gs_workspace_size("raster_fwd", 100, 64, 48, cv) == 0
+    fake = 0x1000
+    buf = (ctypes.c_char * 8192)()
+    ws = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 256
+    f = fake
+    # too many views
+    assert L.lib().gs_raster_fwd(ctypes.byref(_cam(L)), ctypes.byref(cv), 10, f, f, f, f, f, f, f,
+                                 None, None, None, None, ws, 4096, None) == 1
+    assert "n_views" in L.gs_last_error()
+    assert L.lib().gs_sort_views(0, 10, f, f, f, ws, 4096, None) == 1
+    assert L.lib().gs_sort_views(17, 10, f, f, f, ws, 4096, None) == 1
+    # each view's slab must hold the one-view size
+    need = L.gs_workspace_size("sort", 5000, 64, 48, c1)
+    assert L.lib().gs_sort_views(4, 5000, f, f, f, ws, 4 * need - 4096, None) == 2
+    assert "slab" in L.gs_last_error()
+    # cameras of one call share the image size
+    cv.n_views = 2
+    cams = L.camera_array([_cam(L, 64, 48), _cam(L, 64, 40)])
+    assert L.lib().gs_preprocess(cams, ctypes.byref(cv), 5, f, f, f, f, f, f, f, f,
+                                 f, f, f, f, ws, 1 << 30, None) == 1
+    assert "image size" in L.gs_last_error()
+    cams = L.camera_array([_cam(L), _cam(L)])
+    cams[1].znear = 0.0
+    assert L.lib().gs_preprocess_bwd(cams, ctypes.byref(cv), 0, *([None] * 14),
+                                     None) == 1
+    # one view only: the 2D entry and the tile-based baseline
+    cam = _cam(L)
+    assert L.lib().gs_prepare_2d(ctypes.byref(cam), ctypes.byref(cv), 5, f, f, f, f, f, f, f, ws,
+                                 1 << 20, None) == 3
+    assert L.lib().gs_tile_prepare(ctypes.byref(cam), ctypes.byref(cv), 5, f, f, f, f, f, f, ws,
+                                   1 << 20, None) == 3

@@ -122,7 +122,8 @@ def test_finite_differences_on_64_parameters():
     assert err <= 1e-3, err
 
 
-def test_short_fit_lowers_loss():
+@pytest.mark.parametrize("views_per_step", [1, 4])
+def test_short_fit_lowers_loss(views_per_step):
     c = synth.CFG4
     W, H = 160, 90
     cams = [synth.camera_ring(k, 8, width=W, height=H, fx=c["fx"] * W / c["width"]) for k in range(8)]
@@ -136,7 +137,8 @@ def test_short_fit_lowers_loss():
                    for cam in cams]
     p = TR.GaussianParams(t(init.means3d), t(init.scales), t(init.quats), t(init.opacities),
                           t(init.sh))
-    hist = TR.fit(p, cams, targets, steps=80, lr=1e-2, cfg=cfg, log_every=8)
+    hist = TR.fit(p, cams, targets, steps=80 if views_per_step == 1 else 40, lr=1e-2, cfg=cfg,
+                  log_every=8 if views_per_step == 1 else 4, views_per_step=views_per_step)
     first = np.mean([l for _, l in hist[:2]])
     last = np.mean([l for _, l in hist[-2:]])
     print(hist)
