@@ -330,8 +330,10 @@ __global__ __launch_bounds__(256) void k_raster_setup(
                         Rec r;
                         r.a = make_float4(mx, my, -0.5f * LOG2E * a, b / a);
                         r.b = make_float4(-0.5f * LOG2E * (detf / a), o, cr, cg);
-                        const float pmin = log2f(amin) - log2f(o);
-                        r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, __float_as_uint(pmin), 0u);
+                        const float lo = log2f(o);
+                        const float pmin = log2f(amin) - lo;
+                        r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, __float_as_uint(pmin),
+                                         __float_as_uint(lo));
                         rec[p] = r;
                         const uint32_t tx0 = x0 / TILE, tx1 = (x1 - 1) / TILE;
                         const uint32_t ty0 = y0 / TILE, ty1 = (y1 - 1) / TILE;
@@ -377,6 +379,31 @@ struct Walk {
     int alive[4];
     Rec rec[BATCH];
 };
+
+// alpha = o exp(-q/2) = exp2(log2 o + p) with p = a' u^2 + d' dy^2, u = dx + k dy (the record's
+// pre-scaled LDL^T factors). A lane's four pixels share two columns and two rows, so the row part
+// log2 o + d' dy^2 is formed once per row; each pixel then costs u, a' u, one FMA and the exp2.
+// The forward and the backward evaluate alpha with these same operations, so they take the same
+// alpha_min decisions.
+__device__ __forceinline__ void alpha_rows(const float4& A, const float4& B, float lo,
+                                           const float (&px)[4], const float (&py)[4],
+                                           float (&dx)[2], float (&dy)[2], float (&er)[2]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        dx[j] = px[j] - A.x;          // columns: sub-blocks 0 and 1
+        dy[j] = py[2 * j] - A.y;      // rows: sub-blocks 0 and 2
+        er[j] = fmaf(B.x * dy[j], dy[j], lo);
+    }
+}
+__device__ __forceinline__ float alpha_raw(const float4& A, float dx, float dy, float er) {
+    const float u = fmaf(A.w, dy, dx);
+    return __builtin_amdgcn_exp2f(fmaf(A.z * u, u, er));
+}
+// min(alpha_max, raw) for raw >= 0, as one median-of-three that takes alpha_max from a scalar
+// register (fminf would re-canonicalise it every iteration)
+__device__ __forceinline__ float clamp_alpha(float raw, float amax) {
+    return __builtin_amdgcn_fmed3f(raw, 0.f, amax);
+}
 
 // Per-wave culling of a staged batch. Lane j takes staged splat k0 + j and bounds its exponent
 // over each of the wave's four 8x8 sub-blocks: with c the sub-block centre and g the gradient of
@@ -602,14 +629,15 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                     const int k = (int)(ent & 0xFFu);
                     const float4 A = w.rec[k].a;
                     const float4 B = w.rec[k].b;
-                    const float cb = __uint_as_float(w.rec[k].c.x);
+                    const uint4 Cw = w.rec[k].c;
+                    const float cb = __uint_as_float(Cw.x);
+                    // the exponent's row part (log2 o folded in) for the lane's two pixel rows
+                    float dxs[2], dys[2], er[2];
+                    alpha_rows(A, B, __uint_as_float(Cw.w), px, py, dxs, dys, er);
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
                         if (((ent >> (8 + s)) & 1u) && (!TCULL || ((alive >> s) & 1u))) {
-                            const float dx = px[s] - A.x, dy = py[s] - A.y;
-                            const float u = fmaf(A.w, dy, dx);
-                            const float pw = fmaf(A.z * u, u, B.x * dy * dy);
-                            const float al = fminf(amax, B.y * __builtin_amdgcn_exp2f(pw));
+                            const float al = clamp_alpha(alpha_raw(A, dxs[s & 1], dys[s >> 1], er[s >> 1]), amax);
                             bool pass = al >= amin;
                             if (TCULL) pass = pass && T[s] >= tmin;
                             if (pass) {
@@ -905,6 +933,9 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                 const uint4 Cw = w.rec[k].c;
                 const float cr = B.z, cg = B.w, cb = __uint_as_float(Cw.x);
                 float* gp = grad + (size_t)uniform(Cw.y) * GRAD_STRIDE;
+                float dxs[2], dys[2], er[2];
+                alpha_rows(A, B, __uint_as_float(Cw.w), px, py, dxs, dys, er);
+                const float inv_o = __builtin_amdgcn_rcpf(B.y);
                 float acc[9];
 #pragma unroll
                 for (int j = 0; j < 9; ++j) acc[j] = 0.f;
@@ -912,13 +943,12 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     if (!((ent >> (8 + s)) & 1u) || !((alive >> s) & 1u)) continue;
-                    const float dx = px[s] - A.x, dy = py[s] - A.y;
+                    const float dx = dxs[s & 1], dy = dys[s >> 1];
                     const float u = fmaf(A.w, dy, dx);
                     const float au = A.z * u;
-                    const float pw = fmaf(au, u, B.x * dy * dy);
-                    const float e = __builtin_amdgcn_exp2f(pw);       // exp(-q/2)
-                    const float araw = B.y * e;
-                    const float al = fminf(amax, araw);
+                    // the forward's alpha (alpha_raw), with a' u kept for the gradient
+                    const float araw = __builtin_amdgcn_exp2f(fmaf(au, u, er[s >> 1]));
+                    const float al = clamp_alpha(araw, amax);
                     // cullingFlag: splat boundary (alpha < 1/255), then T-Culling (T < 1e-4)
                     const bool live = valid[s] && al >= amin && T[s] >= tmin;
                     float g[9];
@@ -953,7 +983,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
                         if (araw < amax) {
                             const float gq = -0.5f * ga * araw;          // dL/dq
                             const float gm = -2.f * ga * araw * (1.0f / LOG2E);
-                            g[5] = ga * e;
+                            g[5] = ga * araw * inv_o;               // dalpha/do = exp(-q/2)
                             g[0] = gm * au;
                             g[1] = gm * fmaf(A.w, au, B.x * dy);
                             g[2] = gq * dx * dx;
