@@ -262,29 +262,97 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 }
 
 // ---- setup: records, tile rectangles, occupancy bitmap and tile weights ---------------------
-// One workgroup per SETUP_SPAN consecutive sorted positions = one 32-bit column of the bitmap
-// (32 chunks of 64 splats). The workgroup gathers, in LDS, one word of chunk bits and one splat
-// count per tile, then writes its bitmap column with plain stores and adds its counts to the tile
-// weights: one global atomic per (workgroup, touched tile), none contended within an instruction.
+// Two kernels. k_raster_pack runs in splat-id order: it reads the caller's arrays coalesced and
+// writes each splat's record fields and tile rectangle as one 64-byte IdRec. k_raster_setup runs
+// in sorted order: one workgroup per SETUP_SPAN consecutive sorted positions = one 32-bit column
+// of the bitmap (32 chunks of 64 splats); each thread gathers its eight splats' IdRecs by id (one
+// cache line each, all eight in flight), writes the sorted records, and the workgroup gathers, in
+// LDS, one word of chunk bits and one splat count per tile, then writes its bitmap column with
+// plain stores and adds its counts to the tile weights: one global atomic per (workgroup, touched
+// tile), none contended within an instruction. The LDS arrays are sized to the image's tiles at
+// launch (8 B per tile), so that several workgroups share a CU. The (splat, tile) pairs of each
+// round of 256 splats are spread evenly over the threads: a scan of the splats' pair counts gives
+// each thread an equal run of consecutive pairs, whose first owner a binary search finds; the
+// thread then walks the run tile by tile. One splat may cover every tile of the image, and a
+// thread walking its own splats' tiles would leave the workgroup waiting on it.
 constexpr int SETUP_SPAN = 32 * CHUNK_SPLATS;   // 2048 sorted positions per workgroup
+constexpr int SETUP_PER_THREAD = SETUP_SPAN / 256;
 constexpr int MAX_LDS_TILES = 8192;
+constexpr uint32_t NO_TILE_X = 0xFFFFu;         // rect.x of a splat that touches no tile
 
-__global__ __launch_bounds__(256) void k_raster_setup(
-    int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
-    const float* __restrict__ means2d, const float* __restrict__ conics,
+struct IdRec {
+    Rec r;          // c.y (the sorted position) is filled in by k_raster_setup
+    uint2 rect;     // tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16)
+    uint2 pad;
+};
+static_assert(sizeof(IdRec) == 64, "one cache line per splat");
+
+__global__ __launch_bounds__(256) void k_raster_pack(
+    int n, const float* __restrict__ means2d, const float* __restrict__ conics,
     const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
-    int saturate, int tiles_x, int ntiles, Rec* __restrict__ rec, uint2* __restrict__ rect,
-    uint32_t* __restrict__ weights, uint32_t* __restrict__ bits, int wpr,
-    uint16_t* __restrict__ colcnt, uint64_t vws) {
-    __shared__ uint32_t s_bits[MAX_LDS_TILES];
-    __shared__ uint32_t s_cnt[MAX_LDS_TILES];
-    sorted_ids = view_at(sorted_ids, (uint64_t)n);
-    nvis_ptr = view_at(nvis_ptr, 1);
+    int saturate, IdRec* __restrict__ out, uint64_t vws) {
     means2d = view_at(means2d, 2ull * n);
     conics = view_at(conics, 3ull * n);
     rgb = view_at(rgb, 3ull * n);          // opacities are the views' shared [n]
+    out = view_bytes(out, vws);
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const float mx = means2d[2 * (size_t)id], my = means2d[2 * (size_t)id + 1];
+    const float a = conics[3 * (size_t)id], b = conics[3 * (size_t)id + 1],
+                c = conics[3 * (size_t)id + 2];
+    const float o = opac[id];
+    float cr = rgb[3 * (size_t)id], cg = rgb[3 * (size_t)id + 1], cb = rgb[3 * (size_t)id + 2];
+    if (saturate) { cr = fminf(cr, 1.f); cg = fminf(cg, 1.f); cb = fminf(cb, 1.f); }
+    IdRec q;
+    q.r.a = make_float4(0.f, 0.f, 0.f, 0.f);
+    q.r.b = make_float4(0.f, 0.f, 0.f, 0.f);
+    q.r.c = make_uint4(0u, 0u, 0u, 0u);
+    q.rect = make_uint2(NO_TILE_X, 0u);
+    q.pad = make_uint2(0u, 0u);
+    // det in FP64: the products of FP32 values are exact, so its sign is exact and its one
+    // rounding leaves it accurate to FP32 even when a c and b^2 nearly cancel
+    const double det = (double)a * c - (double)b * b;
+    if (a > 0.f && c > 0.f && det > 0.0 && o >= amin && isfinite(mx) && isfinite(my)) {
+        const float detf = (float)det;
+        // alpha >= alpha_min  <=>  q <= r2 = 2 ln(o / alpha_min): the ellipse's half extents are
+        // sqrt(r2 Sigma_xx), sqrt(r2 Sigma_yy) with Sigma = conic^-1; padded so FP32 rounding
+        // never puts a passing pixel outside the box.
+        const float r2 = 2.0f * logf(o / amin);
+        const float hx = sqrtf(fmaxf(r2 * c / detf, 0.f)) * 1.001f + 0.01f;
+        const float hy = sqrtf(fmaxf(r2 * a / detf, 0.f)) * 1.001f + 0.01f;
+        const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
+        const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), (float)W);
+        const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
+        const float fy1 = fminf(fmaxf(floorf(my + hy - 0.5f) + 1.f, 0.f), (float)H);
+        if (fx0 < fx1 && fy0 < fy1) {
+            const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
+            const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
+            q.r.a = make_float4(mx, my, -0.5f * LOG2E * a, b / a);
+            q.r.b = make_float4(-0.5f * LOG2E * (detf / a), o, cr, cg);
+            const float lo = log2f(o);
+            const float pmin = log2f(amin) - lo;
+            q.r.c = make_uint4(__float_as_uint(cb), 0u, __float_as_uint(pmin), __float_as_uint(lo));
+            q.rect = make_uint2((x0 / TILE) | (((x1 - 1) / TILE) << 16),
+                                (y0 / TILE) | (((y1 - 1) / TILE) << 16));
+        }
+    }
+    out[id] = q;
+}
+
+__global__ __launch_bounds__(256, 4) void k_raster_setup(
+    int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
+    const IdRec* __restrict__ idrec, int tiles_x, int ntiles, Rec* __restrict__ rec,
+    uint2* __restrict__ rect, int32_t* __restrict__ inv, uint32_t* __restrict__ weights,
+    uint32_t* __restrict__ bits, int wpr, uint16_t* __restrict__ colcnt, uint64_t vws) {
+    extern __shared__ uint32_t s_dyn[];   // [2][ntiles] when ntiles <= MAX_LDS_TILES
+    uint32_t* s_bits = s_dyn;
+    uint32_t* s_cnt = s_dyn + ntiles;
+    sorted_ids = view_at(sorted_ids, (uint64_t)n);
+    nvis_ptr = view_at(nvis_ptr, 1);
+    idrec = view_bytes(idrec, vws);
     rec = view_bytes(rec, vws);
     rect = view_bytes(rect, vws);
+    inv = view_bytes(inv, vws);
     weights = view_bytes(weights, vws);
     bits = view_bytes(bits, vws);
     colcnt = view_bytes(colcnt, vws);
@@ -295,67 +363,86 @@ __global__ __launch_bounds__(256) void k_raster_setup(
     int nvis = *nvis_ptr;
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     const int p0 = blockIdx.x * SETUP_SPAN;
-    for (int j = 0; j < SETUP_SPAN / 256; ++j) {
+    int ids[SETUP_PER_THREAD];
+#pragma unroll
+    for (int j = 0; j < SETUP_PER_THREAD; ++j) {
         const int p = p0 + j * 256 + threadIdx.x;
-        if (p >= n) break;
-        uint2 rr = make_uint2(0xFFFFu, 0u);   // matches no tile
-        if (p < nvis) {
-            const int id = sorted_ids[p];
-            if ((unsigned)id < (unsigned)n) {
-                const float mx = means2d[2 * (size_t)id], my = means2d[2 * (size_t)id + 1];
-                const float a = conics[3 * (size_t)id], b = conics[3 * (size_t)id + 1],
-                            c = conics[3 * (size_t)id + 2];
-                const float o = opac[id];
-                float cr = rgb[3 * (size_t)id], cg = rgb[3 * (size_t)id + 1],
-                      cb = rgb[3 * (size_t)id + 2];
-                if (saturate) { cr = fminf(cr, 1.f); cg = fminf(cg, 1.f); cb = fminf(cb, 1.f); }
-                // det in FP64: the products of FP32 values are exact, so its sign is exact and
-                // its one rounding leaves it accurate to FP32 even when a c and b^2 nearly cancel
-                const double det = (double)a * c - (double)b * b;
-                if (a > 0.f && c > 0.f && det > 0.0 && o >= amin && isfinite(mx) && isfinite(my)) {
-                    const float detf = (float)det;
-                    // alpha >= alpha_min  <=>  q <= r2 = 2 ln(o / alpha_min): the ellipse's half
-                    // extents are sqrt(r2 Sigma_xx), sqrt(r2 Sigma_yy) with Sigma = conic^-1;
-                    // padded so FP32 rounding never puts a passing pixel outside the box.
-                    const float r2 = 2.0f * logf(o / amin);
-                    const float hx = sqrtf(fmaxf(r2 * c / detf, 0.f)) * 1.001f + 0.01f;
-                    const float hy = sqrtf(fmaxf(r2 * a / detf, 0.f)) * 1.001f + 0.01f;
-                    const float fx0 = fminf(fmaxf(floorf(mx - hx - 0.5f), 0.f), (float)W);
-                    const float fx1 = fminf(fmaxf(floorf(mx + hx - 0.5f) + 1.f, 0.f), (float)W);
-                    const float fy0 = fminf(fmaxf(floorf(my - hy - 0.5f), 0.f), (float)H);
-                    const float fy1 = fminf(fmaxf(floorf(my + hy - 0.5f) + 1.f, 0.f), (float)H);
-                    if (fx0 < fx1 && fy0 < fy1) {
-                        const uint32_t x0 = (uint32_t)fx0, x1 = (uint32_t)fx1;
-                        const uint32_t y0 = (uint32_t)fy0, y1 = (uint32_t)fy1;
-                        Rec r;
-                        r.a = make_float4(mx, my, -0.5f * LOG2E * a, b / a);
-                        r.b = make_float4(-0.5f * LOG2E * (detf / a), o, cr, cg);
-                        const float lo = log2f(o);
-                        const float pmin = log2f(amin) - lo;
-                        r.c = make_uint4(__float_as_uint(cb), (uint32_t)p, __float_as_uint(pmin),
-                                         __float_as_uint(lo));
-                        rec[p] = r;
-                        const uint32_t tx0 = x0 / TILE, tx1 = (x1 - 1) / TILE;
-                        const uint32_t ty0 = y0 / TILE, ty1 = (y1 - 1) / TILE;
-                        rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-                        const uint32_t bit = 1u << ((uint32_t)(p - p0) / CHUNK_SPLATS);
-                        for (uint32_t ty = ty0; ty <= ty1; ++ty)
-                            for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-                                const uint32_t t = ty * (uint32_t)tiles_x + tx;
-                                if (in_lds) {
-                                    atomicOr(&s_bits[t], bit);
-                                    atomicAdd(&s_cnt[t], 1u);
-                                } else if (p % WEIGHT_SAMPLE == 0) {
-                                    atomicAdd(&weights[t], 1u);
-                                }
-                            }
-                    }
+        const int id = p < n ? sorted_ids[p] : -1;
+        if ((unsigned)id < (unsigned)n) inv[id] = p;    // sorted position by id, for the backward
+        ids[j] = (p < nvis && (unsigned)id < (unsigned)n) ? id : -1;
+    }
+    IdRec q[SETUP_PER_THREAD];
+#pragma unroll
+    for (int j = 0; j < SETUP_PER_THREAD; ++j)
+        if (ids[j] >= 0) q[j] = idrec[ids[j]];
+    __shared__ uint32_t s_first[257];      // exclusive scan of the round's pair counts
+    __shared__ uint2 s_rect[256];
+    __shared__ uint32_t s_wtot[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = 0; j < SETUP_PER_THREAD; ++j) {
+        const int p = p0 + j * 256 + tid;
+        uint2 rr = make_uint2(NO_TILE_X, 0u);
+        if (p < n && ids[j] >= 0 && q[j].rect.x != NO_TILE_X) {
+            Rec r = q[j].r;
+            r.c.y = (uint32_t)p;
+            rec[p] = r;
+            rr = q[j].rect;
+        }
+        if (p < n) rect[p] = rr;
+        const uint32_t tx0 = rr.x & 0xFFFFu, tx1 = rr.x >> 16;
+        const uint32_t ty0 = rr.y & 0xFFFFu, ty1 = rr.y >> 16;
+        const uint32_t cnt = rr.x != NO_TILE_X ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0u;
+        if (!in_lds) {                     // sampled weights only: each thread walks its own pairs
+            if (p % WEIGHT_SAMPLE == 0 && cnt)
+                for (uint32_t ty = ty0; ty <= ty1; ++ty)
+                    for (uint32_t tx = tx0; tx <= tx1; ++tx)
+                        atomicAdd(&weights[ty * (uint32_t)tiles_x + tx], 1u);
+            continue;
+        }
+        uint32_t incl = cnt;               // inclusive scan over the wave, then over the waves
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) s_wtot[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0u;
+        for (int w2 = 0; w2 < wave; ++w2) before += s_wtot[w2];
+        s_first[tid] = before + incl - cnt;
+        s_rect[tid] = rr;
+        if (tid == 255) s_first[256] = before + incl;
+        __syncthreads();
+        const uint32_t total = s_first[256];
+        const uint32_t per = (total + 255u) / 256u;
+        const uint32_t k0 = min((uint32_t)tid * per, total), k1 = min(k0 + per, total);
+        if (k0 < k1) {
+            int i = 0;                     // owner of pair k0: the last entry whose first pair <= k0
+#pragma unroll
+            for (int step = 128; step > 0; step >>= 1)
+                if (s_first[i + step] <= k0) i += step;
+            uint2 ro = s_rect[i];
+            uint32_t w = (ro.x >> 16) - (ro.x & 0xFFFFu) + 1u;
+            const uint32_t local = k0 - s_first[i];
+            uint32_t ty = (ro.y & 0xFFFFu) + local / w, tx = (ro.x & 0xFFFFu) + local % w;
+            uint32_t next = s_first[i + 1];   // first pair of the next entry
+            for (uint32_t k = k0; k < k1; ++k) {
+                while (k >= next) {           // the run moves on to the next splat with pairs
+                    ++i;
+                    next = s_first[i + 1];
+                    ro = s_rect[i];
+                    w = (ro.x >> 16) - (ro.x & 0xFFFFu) + 1u;
+                    tx = ro.x & 0xFFFFu;
+                    ty = ro.y & 0xFFFFu;
                 }
+                const uint32_t t = ty * (uint32_t)tiles_x + tx;
+                atomicOr(&s_bits[t], 1u << (j * (256 / CHUNK_SPLATS) + i / CHUNK_SPLATS));
+                atomicAdd(&s_cnt[t], 1u);
+                if (++tx > (ro.x >> 16)) { tx = ro.x & 0xFFFFu; ++ty; }
             }
         }
-        rect[p] = rr;
+        __syncthreads();                   // s_first / s_rect are rewritten by the next round
     }
-    __syncthreads();
     if (in_lds)
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
             if (wpr > 0) bits[(size_t)t * wpr + blockIdx.x] = s_bits[t];
@@ -1065,13 +1152,15 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     }
 }
 
-// Scatter the accumulated gradients from sorted position to splat id; zero for culled splats.
+// The accumulated gradients moved from sorted position to splat id, one thread per id: it
+// gathers its splat's slot (found through the setup's inverse permutation) and writes the
+// outputs in id order; zero for culled splats.
 __global__ __launch_bounds__(256) void k_grad_finalize(
-    int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
+    int n, const int32_t* __restrict__ inv, const int32_t* __restrict__ nvis_ptr,
     const float* __restrict__ grad, const float* __restrict__ rgb, int saturate,
     float* __restrict__ g_m, float* __restrict__ g_c, float* __restrict__ g_o,
     float* __restrict__ g_rgb, uint64_t vws) {
-    sorted_ids = view_at(sorted_ids, (uint64_t)n);
+    inv = view_bytes(inv, vws);
     nvis_ptr = view_at(nvis_ptr, 1);
     grad = view_bytes(grad, vws);
     rgb = view_at(rgb, 3ull * n);
@@ -1079,14 +1168,13 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
     g_c = view_at(g_c, 3ull * n);
     g_o = view_at(g_o, (uint64_t)n);
     g_rgb = view_at(g_rgb, 3ull * n);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
     int nvis = *nvis_ptr;
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
-    const int id = sorted_ids[p];
-    if ((unsigned)id >= (unsigned)n) return;
+    const int p = inv[id];
     float v[9];
-    if (p < nvis) {
+    if ((unsigned)p < (unsigned)nvis) {
         const float4* gp = reinterpret_cast<const float4*>(grad + (size_t)p * GRAD_STRIDE);
         const float4 u0 = gp[0], u1 = gp[1];
         const float u2 = grad[(size_t)p * GRAD_STRIDE + 8];
@@ -1152,13 +1240,17 @@ static bool split_ok(int n, int width, int height) {
 size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
     const size_t nt = (size_t)tiles_of(width, height);
     const size_t wpr = (size_t)bitmap_wpr(n, width, height);
-    size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up(16 * 8) +
-               align_up(nt * 4) * 2 + align_up(nt * wpr * 4);
+    size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up((size_t)n * 4) +
+               align_up(16 * 8) + align_up(nt * 4) * 2 + align_up(nt * wpr * 4);
     if (split_ok(n, width, height))
         b += align_up(nt * wpr * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
              2 * align_up(ITEMS_PER_TILE * nt * 4) + 2 * align_up(nt * 4) +
              align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
-    if (bwd) b += align_up((size_t)n * GRAD_STRIDE * 4) + align_up(nt * 16);
+    // the setup's per-id staging and the backward's gradient slots share one region (64 B per
+    // splat): the staging is dead once the setup has run, before the gradients are cleared
+    static_assert(GRAD_STRIDE * 4 == sizeof(IdRec), "shared region");
+    b += align_up((size_t)n * GRAD_STRIDE * 4);
+    if (bwd) b += align_up(nt * 16);
     return b;
 }
 
@@ -1168,6 +1260,7 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     char* p = (char*)ws;
     r.rec = p;      p += align_up((size_t)n * REC_BYTES);
     r.rect = p;     p += align_up((size_t)n * 8);
+    r.inv = (int32_t*)p; p += align_up((size_t)n * 4);
     r.counters = (unsigned long long*)p; p += align_up(16 * 8);
     r.weights = (uint32_t*)p; p += align_up(nt * 4);
     r.order = (int32_t*)p;    p += align_up(nt * 4);
@@ -1185,9 +1278,11 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
         r.tile_k = (int32_t*)p;     p += align_up(nt * 4);
         r.partial = (float4*)p;     p += align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
     }
-    r.grad = nullptr; r.bgpart = nullptr;
+    r.idrec = p;
+    r.grad = bwd ? (float*)p : nullptr;
+    p += align_up((size_t)n * GRAD_STRIDE * 4);
+    r.bgpart = nullptr;
     if (bwd) {
-        r.grad = (float*)p;   p += align_up((size_t)n * GRAD_STRIDE * 4);
         r.bgpart = (float*)p; p += align_up(nt * 16);
     }
     return r;
@@ -1207,10 +1302,14 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
     if (e != hipSuccess) return e;
     if (n > 0) {
         const int sat = (cfg.fb_format == FB_UNORM16 || cfg.fb_format == FB_UNORM8) ? 1 : 0;
-        hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V), dim3(256), 0,
-                           s, n, sorted_ids, n_visible, means2d, conics, opac, rgb, width, height,
-                           cfg.alpha_min, sat, tiles_x, ntiles, (Rec*)r.rec, (uint2*)r.rect,
-                           r.weights, r.bits, r.wpr, r.colcnt, vs.ws);
+        hipLaunchKernelGGL(k_raster_pack, dim3((n + 255) / 256, V), dim3(256), 0, s, n, means2d,
+                           conics, opac, rgb, width, height, cfg.alpha_min, sat, (IdRec*)r.idrec,
+                           vs.ws);
+        const size_t lds = ntiles <= MAX_LDS_TILES ? (size_t)ntiles * 8 : 0;
+        hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V), dim3(256),
+                           lds, s, n, sorted_ids, n_visible, (const IdRec*)r.idrec, tiles_x, ntiles,
+                           (Rec*)r.rec, (uint2*)r.rect, r.inv, r.weights, r.bits, r.wpr, r.colcnt,
+                           vs.ws);
     }
     hipLaunchKernelGGL(k_plan_tiles, dim3(1, V), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
                        r.split, r.tile_k, r.tile_first, r.counters, vs.ws);
@@ -1310,14 +1409,14 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     const RasterWs r = carve_raster_ws(ws, n, width, height, true);
     const int sat = (int)saturating(cfg.fb_format);
     const int V = vs.count;
-    if (n > 0) {
-        hipError_t e = launch_fill_u32(r.grad, (size_t)n * GRAD_STRIDE, 0u, s, V, vs.ws);
-        if (e != hipSuccess) return e;
-    }
     if (!(cfg.flags & GS_FLAG_REUSE_SETUP)) {
         hipError_t e0 = raster_setup(cfg, width, height, n, sorted_ids, n_visible, means2d, conics,
                                      opac, rgb, r, s, vs);
         if (e0 != hipSuccess) return e0;
+    }
+    if (n > 0) {   // after the setup: the gradient slots reuse its staging region
+        hipError_t e = launch_fill_u32(r.grad, (size_t)n * GRAD_STRIDE, 0u, s, V, vs.ws);
+        if (e != hipSuccess) return e;
     }
     const int tiles_x = (width + TILE - 1) / TILE;
     const int nblocks = tiles_of(width, height);
@@ -1358,8 +1457,9 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
         if (e != hipSuccess) return e;
     }
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256, V), dim3(256), 0, s, n, sorted_ids,
-                       n_visible, r.grad, rgb, sat, g_means2d, g_conics, g_opac, g_rgb, vs.ws);
+    hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256, V), dim3(256), 0, s, n,
+                       (const int32_t*)r.inv, n_visible, r.grad, rgb, sat, g_means2d, g_conics,
+                       g_opac, g_rgb, vs.ws);
     return hipGetLastError();
 }
 

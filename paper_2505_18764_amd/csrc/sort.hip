@@ -165,18 +165,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
         for (int w = 0; w < 4; ++w) s_cnt[b][w][tid] = 0;
     __syncthreads();
     const uint64_t lt = mask_lt(lane);
+    // all of the block's pairs are loaded up front, so the rounds below wait on no global load
+    K kr[SORT_ROUNDS];
+    int32_t vr[SORT_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int idx = start + r * SORT_THREADS + tid;
+        kr[r] = idx < n ? kin[idx] : K(0);
+        vr[r] = idx < n ? vin[idx] : 0;
+    }
+#pragma unroll
     for (int r = 0; r < SORT_ROUNDS; ++r) {
         const int buf = r & 1;
         const int idx = start + r * SORT_THREADS + tid;
         const bool valid = idx < n;
-        K key = 0;
-        int32_t val = 0;
-        uint32_t d = 0;
-        if (valid) {
-            key = kin[idx];
-            val = vin[idx];
-            d = (uint32_t)(key >> shift) & 0xFFu;
-        }
+        const K key = kr[r];
+        const int32_t val = vr[r];
+        const uint32_t d = valid ? (uint32_t)(key >> shift) & 0xFFu : 0u;
         // lanes of this wave with the same digit
         uint64_t peers = ballot(valid);
         for (int b = 0; b < 8; ++b) {
@@ -256,10 +261,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact_scatter(
     uint32_t vis_run = offs[blockIdx.x];
     uint32_t cul_run = total + ((uint32_t)start - offs[blockIdx.x]);
     const uint64_t lt = mask_lt(lane);
+    uint32_t kr[SORT_ROUNDS];               // loaded up front, as in the sort's scatter
+#pragma unroll
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int i = start + r * SORT_THREADS + tid;
+        kr[r] = i < n ? kid[i] : 0xFFFFFFFFu;
+    }
+#pragma unroll
     for (int r = 0; r < SORT_ROUNDS; ++r) {
         const int i = start + r * SORT_THREADS + tid;
         const bool in = i < n;
-        const uint32_t k = in ? kid[i] : 0xFFFFFFFFu;
+        const uint32_t k = kr[r];
         const bool v = in && k != 0xFFFFFFFFu;
         const uint64_t mv = ballot(v), mc = ballot(in && !v);
         if (lane == 0) { s_w[0][wave] = popc(mv); s_w[1][wave] = popc(mc); }
