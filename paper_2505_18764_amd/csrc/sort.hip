@@ -54,7 +54,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const K* __restrict_
     hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
-// Exclusive scan of `count` uint32 in three launches: block sums, scan of the sums, apply.
+// Exclusive scan of `count` uint32: block sums, scan of the sums, apply (the middle launch is
+// skipped when the blocks are few enough for each to add up its predecessors itself).
 // Batched over views: `in`, `out` and `sums` of view v are `vws` bytes after view v - 1's.
 __global__ __launch_bounds__(256) void k_scan_sums(const uint32_t* __restrict__ in, size_t count,
                                                    uint32_t* __restrict__ sums, uint64_t vws) {
@@ -100,14 +101,28 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ sums, 
         }
 }
 
+// With `raw_sums`, sums[] holds the blocks' totals (not yet scanned) and each block adds those of
+// the blocks before it itself, which saves the launch of k_scan_top when the blocks are few.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, size_t count,
                                                     const uint32_t* __restrict__ sums,
-                                                    uint32_t* __restrict__ out, uint64_t vws) {
+                                                    uint32_t* __restrict__ out, uint64_t vws,
+                                                    int raw_sums) {
     // each thread owns 16 consecutive entries of the block's 4096
     __shared__ uint32_t part[256];
+    __shared__ uint32_t s_red[4];
     in = view_bytes(in, vws);
     sums = view_bytes(sums, vws);
     out = view_bytes(out, vws);
+    uint32_t before = 0u;
+    if (raw_sums) {
+        for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) before += sums[b];
+        for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o);
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = before;
+        __syncthreads();
+        before = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    } else {
+        before = sums[blockIdx.x];
+    }
     const size_t base = (size_t)blockIdx.x * SCAN_ITEMS + (size_t)threadIdx.x * 16;
     uint32_t v[16];
     uint32_t s = 0;
@@ -123,7 +138,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
         part[threadIdx.x] += t;
         __syncthreads();
     }
-    uint32_t run = sums[blockIdx.x] + (threadIdx.x ? part[threadIdx.x - 1] : 0u);
+    uint32_t run = before + (threadIdx.x ? part[threadIdx.x - 1] : 0u);
     for (int j = 0; j < 16; ++j)
         if (base + j < count) {
             out[base + j] = run;
@@ -131,15 +146,56 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
         }
 }
 
+// One workgroup scans up to SCAN_ONE_MAX entries in one launch (e.g. the compaction's block
+// counts): thread t sums its contiguous run of at most 4 entries, the 1024 run sums are scanned
+// (within each wave by shuffles, then over the 16 waves), and each thread writes its run's
+// prefixes. `in` and `out` may alias. Longer arrays take the three-launch scan: one workgroup
+// cannot keep enough loads in flight to read them quickly.
+constexpr int SCAN_ONE_THREADS = 1024;
+constexpr size_t SCAN_ONE_MAX = (size_t)SCAN_ONE_THREADS * 4;
+
+__global__ __launch_bounds__(SCAN_ONE_THREADS) void k_scan_one(const uint32_t* in, size_t count,
+                                                               uint32_t* out, uint64_t vws) {
+    __shared__ uint32_t s_wave[SCAN_ONE_THREADS / 64];
+    in = view_bytes(in, vws);
+    out = view_bytes(out, vws);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t per = (count + SCAN_ONE_THREADS - 1) / SCAN_ONE_THREADS;
+    const size_t lo = min((size_t)tid * per, count), hi = min(lo + per, count);
+    uint32_t run = 0u;
+    for (size_t i = lo; i < hi; ++i) run += in[i];
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t base = incl - run;
+    for (int w = 0; w < wave; ++w) base += s_wave[w];
+    for (size_t i = lo; i < hi; ++i) {
+        const uint32_t v = in[i];
+        out[i] = base;
+        base += v;
+    }
+}
+
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t count, uint32_t* sums,
                                  hipStream_t s, const Views& vs) {
     if (count == 0) return hipSuccess;
+    if (count <= SCAN_ONE_MAX) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1, vs.count), dim3(SCAN_ONE_THREADS), 0, s, in, count,
+                           out, vs.ws);
+        return hipGetLastError();
+    }
     const int blocks = (int)((count + SCAN_ITEMS - 1) / SCAN_ITEMS);
     const int V = vs.count;
     hipLaunchKernelGGL(k_scan_sums, dim3(blocks, V), dim3(256), 0, s, in, count, sums, vs.ws);
-    hipLaunchKernelGGL(k_scan_top, dim3(1, V), dim3(1024), 0, s, sums, blocks, vs.ws);
+    const int raw = blocks <= 256 ? 1 : 0;   // few blocks: each adds its predecessors' totals
+    if (!raw) hipLaunchKernelGGL(k_scan_top, dim3(1, V), dim3(1024), 0, s, sums, blocks, vs.ws);
     hipLaunchKernelGGL(k_scan_apply, dim3(blocks, V), dim3(256), 0, s, in, count, sums, out,
-                       vs.ws);
+                       vs.ws, raw);
     return hipGetLastError();
 }
 
