@@ -74,36 +74,48 @@ constexpr int MAX_SPLIT_TILES = 4096;
 constexpr int SEG_DIV = 3;
 constexpr int ITEMS_PER_TILE = SEG_DIV + 1;
 
+// Exclusive scan of one value per thread over a workgroup of NBUCKETS (1024) threads: within each
+// wave by shuffles, then over the 16 wave totals. Returns the prefix; *total gets the sum.
+__device__ uint32_t block_scan_1024(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t s_wtot[NBUCKETS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_wtot[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0u, all = 0u;
+#pragma unroll
+    for (int w2 = 0; w2 < NBUCKETS / 64; ++w2) {
+        const uint32_t t = s_wtot[w2];
+        before += w2 < wave ? t : 0u;
+        all += t;
+    }
+    __syncthreads();                      // s_wtot may be reused by the next call
+    if (total) *total = all;
+    return before + incl - v;
+}
+
 // out[0 .. count) = indices ordered by decreasing bucket of w (one workgroup of 1024 threads);
-// out[count .. pad) = -1.
+// out[count .. pad) = -1. Buckets split [0, wmax] evenly; the order within a bucket is arbitrary.
 __device__ void bucket_order(const uint32_t* __restrict__ w, int count, uint32_t wmax,
                              int32_t* __restrict__ out, int pad, uint32_t* s_hist) {
     const int tid = threadIdx.x;
     for (int b = tid; b < NBUCKETS; b += blockDim.x) s_hist[b] = 0u;
     __syncthreads();
-    const unsigned long long den = (unsigned long long)wmax + 1ull;
-    for (int i = tid; i < count; i += blockDim.x) {
-        const int b = NBUCKETS - 1 - (int)((unsigned long long)w[i] * NBUCKETS / den);
-        atomicAdd(&s_hist[b], 1u);
-    }
+    const float scale = (float)NBUCKETS / ((float)wmax + 1.0f);
+    auto bucket = [&](uint32_t x) {
+        return NBUCKETS - 1 - min((int)((float)x * scale), NBUCKETS - 1);
+    };
+    for (int i = tid; i < count; i += blockDim.x) atomicAdd(&s_hist[bucket(w[i])], 1u);
     __syncthreads();
-    // exclusive scan of the NBUCKETS counts (blockDim.x == NBUCKETS)
-    uint32_t v = s_hist[tid];
+    const uint32_t first = block_scan_1024(s_hist[tid], nullptr);   // blockDim.x == NBUCKETS
+    s_hist[tid] = first;
     __syncthreads();
-    for (int o = 1; o < NBUCKETS; o <<= 1) {
-        const uint32_t add = tid >= o ? s_hist[tid - o] : 0u;
-        __syncthreads();
-        s_hist[tid] += add;
-        __syncthreads();
-    }
-    const uint32_t incl = s_hist[tid];
-    __syncthreads();
-    s_hist[tid] = incl - v;
-    __syncthreads();
-    for (int i = tid; i < count; i += blockDim.x) {
-        const int b = NBUCKETS - 1 - (int)((unsigned long long)w[i] * NBUCKETS / den);
-        out[atomicAdd(&s_hist[b], 1u)] = i;      // order within a bucket is arbitrary
-    }
+    for (int i = tid; i < count; i += blockDim.x) out[atomicAdd(&s_hist[bucket(w[i])], 1u)] = i;
     for (int i = count + tid; i < pad; i += blockDim.x) out[i] = -1;
 }
 
@@ -138,9 +150,9 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
     __syncthreads();
     // k_t = ceil(w_t / cap), cap = ceil(mean weight / SEG_DIV): sum of k_t <= total / cap +
     // ntiles <= ITEMS_PER_TILE ntiles
-    const unsigned long long cap =
-        max(1ull, (total + (unsigned long long)SEG_DIV * ntiles - 1) /
-                      ((unsigned long long)SEG_DIV * ntiles));
+    // cap <= max weight <= n < 2^31, so the per-tile division below is 32-bit
+    const uint32_t cap = (uint32_t)max(1ull, (total + (unsigned long long)SEG_DIV * ntiles - 1) /
+                                                 ((unsigned long long)SEG_DIV * ntiles));
     // exclusive scan of k_t over tiles: thread tid owns tiles [4 tid, 4 tid + 4) (ntiles <= 4096)
     int kk[4], loc = 0;
 #pragma unroll
@@ -148,29 +160,22 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
         const int t = 4 * tid + r;
         int k = 0;
         if (t < ntiles) {
-            const unsigned long long q = ((unsigned long long)weights[t] + cap - 1) / cap;
-            k = (int)min((unsigned long long)MAX_SEGMENTS, max(1ull, q));
+            const uint32_t q = weights[t] / cap + (weights[t] % cap != 0u);
+            k = (int)min((uint32_t)MAX_SEGMENTS, max(1u, q));
             tile_k[t] = k;
         }
         kk[r] = k;
         loc += k;
     }
-    s_hist[tid] = (uint32_t)loc;
-    __syncthreads();
-    for (int o = 1; o < NBUCKETS; o <<= 1) {
-        const uint32_t add = tid >= o ? s_hist[tid - o] : 0u;
-        __syncthreads();
-        s_hist[tid] += add;
-        __syncthreads();
-    }
-    int run = (int)s_hist[tid] - loc;
+    uint32_t nitems = 0u;
+    int run = (int)block_scan_1024((uint32_t)loc, &nitems);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int t = 4 * tid + r;
         if (t < ntiles) tile_first[t] = run;
         run += kk[r];
     }
-    if (tid == NBUCKETS - 1) counters[0] = (unsigned long long)s_hist[tid];
+    if (tid == 0) counters[0] = (unsigned long long)nitems;
 }
 
 // One wave per tile: the tile's work items. A tile with k_t = 1 is one item over all columns
@@ -196,31 +201,38 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
     }
     __shared__ int cut[MAX_SEGMENTS + 1];            // in LDS: indexed by a runtime j below
     __shared__ uint32_t cum[MAX_SEGMENTS + 1];
+    __shared__ uint32_t tgt[MAX_SEGMENTS];           // cut j where the count first reaches tgt[j]
     if (lane <= MAX_SEGMENTS) { cut[lane] = lane ? wpr : 0; cum[lane] = lane ? w : 0u; }
+    if (lane < MAX_SEGMENTS) tgt[lane] = (uint32_t)(((unsigned long long)w * lane + k - 1) / k);
     __syncthreads();
     int found = 1;                                   // next cut to find
     uint32_t base = 0u;
     const uint16_t* row = colcnt + (size_t)t * wpr;
-    for (int c0 = 0; c0 < wpr && found < k; c0 += 64) {
-        uint32_t v = (c0 + lane < wpr) ? row[c0 + lane] : 0u;
+    // the first PRE chunks of 64 columns are loaded together, later ones one at a time
+    constexpr int PRE = 16;
+    uint32_t pre[PRE];
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) pre[i] = (i * 64 + lane < wpr) ? row[i * 64 + lane] : 0u;
+    auto chunk = [&](int c0, uint32_t v) {
         for (int o = 1; o < 64; o <<= 1) {          // inclusive prefix over the wave
             const uint32_t u = __shfl_up(v, o);
             if (lane >= o) v += u;
         }
         const uint32_t incl = base + v;
-#pragma unroll
-        for (int j = 1; j < MAX_SEGMENTS; ++j) {
-            if (j >= k || j < found) continue;
-            const uint32_t target = (uint32_t)(((unsigned long long)w * j + k - 1) / k);
-            const uint64_t m = ballot(incl >= target && c0 + lane < wpr);
-            if (m) {
-                const int l = __builtin_ctzll(m);
-                if (lane == l) { cut[j] = c0 + l + 1; cum[j] = incl; }
-                found = j + 1;
-            }
+        for (int j = found; j < k; ++j) {
+            const uint64_t m = ballot(incl >= tgt[j] && c0 + lane < wpr);
+            if (!m) break;                          // later targets are larger still
+            const int l = __builtin_ctzll(m);
+            if (lane == l) { cut[j] = c0 + l + 1; cum[j] = incl; }
+            found = j + 1;
         }
         base = __shfl(incl, 63);
-    }
+    };
+#pragma unroll
+    for (int i = 0; i < PRE; ++i)
+        if (i * 64 < wpr && found < k) chunk(i * 64, pre[i]);
+    for (int c0 = PRE * 64; c0 < wpr && found < k; c0 += 64)
+        chunk(c0, (c0 + lane < wpr) ? row[c0 + lane] : 0u);
     __syncthreads();
     if (lane == 0) {
         cut[k] = wpr; cum[k] = w;
