@@ -56,6 +56,8 @@ struct RasterWs {
     unsigned long long* counters;  // [16] planner scratch
     uint32_t* weights; // [tiles] splat count per tile
     int32_t* order;    // [tiles] tiles, heaviest first
+    uint32_t* bwd_w;   // [tiles] the backward's walk length per tile (forward's estimate)
+    int32_t* bwd_order; // [tiles] tiles by bwd_w, heaviest first
     uint32_t* bits;    // [tiles][wpr] occupancy bitmap: one bit per 64 sorted splats
     int wpr;           // words per bitmap row (0: no bitmap)
     // depth-split forward (split != 0): per-tile splat counts of each 2048-position column,

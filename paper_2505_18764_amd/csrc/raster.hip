@@ -125,7 +125,7 @@ __device__ void bucket_order(const uint32_t* __restrict__ w, int count, uint32_t
 __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
     const uint32_t* __restrict__ weights, int ntiles, int32_t* __restrict__ order, int split,
     int32_t* __restrict__ tile_k, int32_t* __restrict__ tile_first,
-    unsigned long long* __restrict__ counters, uint64_t vws) {
+    unsigned long long* __restrict__ counters, uint32_t* __restrict__ bwd_w, uint64_t vws) {
     __shared__ uint32_t s_hist[NBUCKETS];
     __shared__ unsigned long long s_tot;
     __shared__ uint32_t s_max;
@@ -134,7 +134,9 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
     tile_k = view_bytes(tile_k, vws);
     tile_first = view_bytes(tile_first, vws);
     counters = view_bytes(counters, vws);
+    bwd_w = view_bytes(bwd_w, vws);
     const int tid = threadIdx.x;
+    for (int t = tid; t < ntiles; t += blockDim.x) bwd_w[t] = weights[t];   // see k_raster_fwd
     if (tid == 0) { s_tot = 0ull; s_max = 0u; }
     __syncthreads();
     unsigned long long tot = 0ull;
@@ -262,6 +264,24 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_items(
     atomicMax(&s_max, mx);
     __syncthreads();
     bucket_order(item_w, count, s_max, item_order, cap, s_hist);
+}
+
+// One workgroup: the backward's tile order, heaviest first by bwd_w (the forward's estimate of
+// each tile's backward walk, else its whole weight).
+__global__ __launch_bounds__(NBUCKETS) void k_plan_bwd(const uint32_t* __restrict__ bwd_w,
+                                                       int ntiles, int32_t* __restrict__ order,
+                                                       uint64_t vws) {
+    __shared__ uint32_t s_hist[NBUCKETS];
+    __shared__ uint32_t s_max;
+    bwd_w = view_bytes(bwd_w, vws);
+    order = view_bytes(order, vws);
+    if (threadIdx.x == 0) s_max = 0u;
+    __syncthreads();
+    uint32_t mx = 0u;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) mx = max(mx, bwd_w[t]);
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    bucket_order(bwd_w, ntiles, s_max, order, ntiles, s_hist);
 }
 
 __device__ __forceinline__ bool rect_hit(uint2 r, uint32_t tx, uint32_t ty) {
@@ -652,12 +672,14 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x, int ntiles,
     const int4* __restrict__ items, const int32_t* __restrict__ item_order,
     float4* __restrict__ partial,
-    float amin, float amax, float tmin, float bg0, float bg1, float bg2, int fb_fmt,
+    float amin, float amax, float tmin, float tsat, float bg0, float bg1, float bg2, int fb_fmt,
     void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T,
-    int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats, uint64_t vws) {
+    int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats,
+    uint32_t* __restrict__ bwd_w, uint64_t vws) {
     __shared__ Walk w;
     if constexpr (MULTI) {   // this view's walk state (its outputs are located at the write-back)
         nvis_ptr = view_at(nvis_ptr, 1);
+        bwd_w = view_bytes(bwd_w, vws);
         rec = view_bytes(rec, vws);
         rect = view_bytes(rect, vws);
         order = view_bytes(order, vws);
@@ -708,6 +730,10 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     const int nch = (nvis + 63) / 64;
     const int cend = c_end >= wpr ? nch : min(nch, c_end * 32);
     int cursor = c_begin * 32;                    // wave 0's position in the walk
+    // the backward's schedule: how many splats this walk takes until every pixel's T is below
+    // the backward's T-cull threshold (the backward stops there); -1 while some pixel is above
+    uint32_t walked = 0;
+    int sat_at = -1;
     for (;;) {
         if (wave == 0) next_round(w, trow, cend, lane, cursor);
         __syncthreads();
@@ -761,12 +787,27 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                     }
                 }
             }
-            if (TCULL && lane == 0) w.alive[wave] = (int)alive;
+            int live_w = 0;
+            if (TCULL) {
+                live_w = (int)alive;
+            } else if (sat_at < 0) {
+                bool a = false;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) a = a || (valid[s] && T[s] >= tsat);
+                live_w = ballot(a) != 0ull;
+            }
+            if (lane == 0) w.alive[wave] = live_w;
             __syncthreads();
-            if (TCULL && !(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3])) { stop = true; break; }
+            const bool all_done = !(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3]);
+            if (all_done && sat_at < 0) sat_at = (int)(walked + (uint32_t)(b0 + m));
+            if (TCULL && all_done) { stop = true; break; }
         }
+        walked += (uint32_t)total;
         if (TCULL && stop) break;
     }
+    // a walk from the front of the tile records where the backward's walk will end; the setup
+    // left the tile's whole weight there for tiles that never get that far
+    if (bwd_w && c_begin == 0 && tid == 0 && sat_at >= 0) bwd_w[tile] = (uint32_t)sat_at;
 
     if (slot >= 0) {                              // a depth segment: FP32 partial state
         float4* part = (MULTI ? view_bytes(partial, vws) : partial) + (size_t)slot * (TILE * TILE);
@@ -1253,7 +1294,7 @@ size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
     const size_t nt = (size_t)tiles_of(width, height);
     const size_t wpr = (size_t)bitmap_wpr(n, width, height);
     size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up((size_t)n * 4) +
-               align_up(16 * 8) + align_up(nt * 4) * 2 + align_up(nt * wpr * 4);
+               align_up(16 * 8) + align_up(nt * 4) * 4 + align_up(nt * wpr * 4);
     if (split_ok(n, width, height))
         b += align_up(nt * wpr * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
              2 * align_up(ITEMS_PER_TILE * nt * 4) + 2 * align_up(nt * 4) +
@@ -1276,6 +1317,8 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     r.counters = (unsigned long long*)p; p += align_up(16 * 8);
     r.weights = (uint32_t*)p; p += align_up(nt * 4);
     r.order = (int32_t*)p;    p += align_up(nt * 4);
+    r.bwd_w = (uint32_t*)p;   p += align_up(nt * 4);
+    r.bwd_order = (int32_t*)p; p += align_up(nt * 4);
     r.wpr = bitmap_wpr(n, width, height);
     r.bits = (uint32_t*)p;    p += align_up(nt * (size_t)r.wpr * 4);
     r.split = split_ok(n, width, height) ? 1 : 0;
@@ -1324,7 +1367,7 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
                            vs.ws);
     }
     hipLaunchKernelGGL(k_plan_tiles, dim3(1, V), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
-                       r.split, r.tile_k, r.tile_first, r.counters, vs.ws);
+                       r.split, r.tile_k, r.tile_first, r.counters, r.bwd_w, vs.ws);
     if (r.split) {
         hipLaunchKernelGGL(k_plan_cuts, dim3(ntiles, V), dim3(64), 0, s, r.weights,
                            (const uint16_t*)r.colcnt, r.wpr, ntiles, (const int32_t*)r.tile_k,
@@ -1349,8 +1392,8 @@ hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int 
 
 using FwdKernel = void (*)(int, const int32_t*, const Rec*, const uint2*, const int32_t*,
                           const uint32_t*, int, int, int, int, int, const int4*, const int32_t*,
-                          float4*, float, float, float, float, float, float, int, void*, float*,
-                          float*, int32_t*, unsigned long long*, uint64_t);
+                          float4*, float, float, float, float, float, float, float, int, void*,
+                          float*, float*, int32_t*, unsigned long long*, uint32_t*, uint64_t);
 
 template <bool TC, bool IN, bool MU>
 static FwdKernel fwd_by_fmt(int rfmt) {
@@ -1397,10 +1440,11 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                        (const uint32_t*)r.bits, r.wpr, width, height, tiles_x, ntiles,
                        split ? (const int4*)r.items : nullptr,
                        split ? (const int32_t*)r.item_order : nullptr, split ? r.partial : nullptr,
-                       cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.background[0],
+                       cfg.alpha_min, cfg.alpha_max, cfg.t_min_fwd, cfg.t_min_bwd, cfg.background[0],
                        cfg.background[1], cfg.background[2], cfg.fb_format, fb, out_rgb, out_T,
                        out_cov,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr,
+                       r.bwd_w,
                        vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !split) return e;
@@ -1432,6 +1476,8 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     }
     const int tiles_x = (width + TILE - 1) / TILE;
     const int nblocks = tiles_of(width, height);
+    hipLaunchKernelGGL(k_plan_bwd, dim3(1, V), dim3(NBUCKETS), 0, s, (const uint32_t*)r.bwd_w,
+                       nblocks, r.bwd_order, vs.ws);
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_live;
     void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
@@ -1453,7 +1499,7 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     }
 #undef GSR_BWD_PICK
     hipLaunchKernelGGL(k, dim3(nblocks, V), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
-                       (const uint2*)r.rect, (const int32_t*)r.order, (const uint32_t*)r.bits,
+                       (const uint2*)r.rect, (const int32_t*)r.bwd_order, (const uint32_t*)r.bits,
                        r.wpr, width, height, tiles_x,
                        cfg.alpha_min, cfg.alpha_max, cfg.t_min_bwd, cfg.fb_format, fb, dL_dimg,
                        dL_dT, cfg.reduce_mode, cfg.reduce_threshold, r.grad,
