@@ -730,10 +730,11 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     const int nch = (nvis + 63) / 64;
     const int cend = c_end >= wpr ? nch : min(nch, c_end * 32);
     int cursor = c_begin * 32;                    // wave 0's position in the walk
-    // the backward's schedule: how many splats this walk takes until every pixel's T is below
-    // the backward's T-cull threshold (the backward stops there); -1 while some pixel is above
-    uint32_t walked = 0;
-    int sat_at = -1;
+    // The backward's schedule: each wave counts the splats of its culled lists until every one of
+    // its pixels has T below the backward's T-cull threshold, which is the work the backward's
+    // wave will do on this tile (it walks the same lists and stops there).
+    uint32_t wl = 0;
+    bool wsat = false;
     for (;;) {
         if (wave == 0) next_round(w, trow, cend, lane, cursor);
         __syncthreads();
@@ -749,6 +750,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
             const int m = min(BATCH, total - b0);
             if (!TCULL || alive) {
                 const int nlist = cull_batch(w, m, wave, lane, lt, cx0, cy0);
+                if (!wsat) wl += (uint32_t)nlist;
                 for (int i = 0; i < nlist; ++i) {
                     const uint32_t ent = uniform((uint32_t)w.list[wave][i]);
                     const int k = (int)(ent & 0xFFu);
@@ -787,27 +789,37 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                     }
                 }
             }
-            int live_w = 0;
-            if (TCULL) {
-                live_w = (int)alive;
-            } else if (sat_at < 0) {
+            if (!wsat) {
                 bool a = false;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) a = a || (valid[s] && T[s] >= tsat);
-                live_w = ballot(a) != 0ull;
+                wsat = ballot(a) == 0ull;
             }
-            if (lane == 0) w.alive[wave] = live_w;
+            if (TCULL && lane == 0) w.alive[wave] = (int)alive;
             __syncthreads();
-            const bool all_done = !(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3]);
-            if (all_done && sat_at < 0) sat_at = (int)(walked + (uint32_t)(b0 + m));
-            if (TCULL && all_done) { stop = true; break; }
+            if (TCULL && !(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3])) { stop = true; break; }
         }
-        walked += (uint32_t)total;
         if (TCULL && stop) break;
     }
-    // a walk from the front of the tile records where the backward's walk will end; the setup
-    // left the tile's whole weight there for tiles that never get that far
-    if (bwd_w && c_begin == 0 && tid == 0 && sat_at >= 0) bwd_w[tile] = (uint32_t)sat_at;
+    // A walk from the front of the tile knows the backward's work on it: the largest wave count
+    // (the waves run side by side). A first depth segment that leaves some wave unsaturated
+    // keeps the setup's whole tile weight, which is larger.
+    if (bwd_w && c_begin == 0) {
+        __syncthreads();
+        if (lane == 0) w.alive[wave] = (int)(wl | (wsat ? 0u : 0x80000000u));
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t mx = 0u;
+            bool all_sat = true;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t x = (uint32_t)w.alive[v];
+                mx = max(mx, x & 0x7FFFFFFFu);
+                all_sat = all_sat && !(x >> 31);
+            }
+            if (slot < 0 || all_sat) bwd_w[tile] = mx;
+        }
+    }
 
     if (slot >= 0) {                              // a depth segment: FP32 partial state
         float4* part = (MULTI ? view_bytes(partial, vws) : partial) + (size_t)slot * (TILE * TILE);

@@ -51,7 +51,15 @@ def test_tile_baseline_2d(W, H, n, seed):
     mb = R.raster_backward(p, mf["fb"], t(G), cfgt, ws)
     torch.cuda.synchronize()
     assert np.abs(mf["image"].cpu().numpy() - img)[:, ok].max() <= 2e-5
-    assert rel_l2(grads9(mb), grads9(b)) <= 2e-4
+    gm, gb = grads9(mb), grads9(b)
+    e_mb = rel_l2(gm, gb)
+    if e_mb > 2e-4:     # name the splats that differ, against the oracle too
+        d = np.abs(gm - gb).max(axis=1)
+        for i in np.argsort(-d)[:5]:
+            print("splat", i, "main", gm[i], "tile", gb[i], "oracle", ref["grad"][i])
+        print("main vs oracle", group_errors(gm, ref["grad"]), "tile vs oracle",
+              group_errors(gb, ref["grad"]))
+    assert e_mb <= 2e-4
 
 
 def test_tile_baseline_on_projected_scene():
