@@ -979,8 +979,10 @@ __device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Wa
     for (int j = 0; j < 9; ++j) tg[tid * 9 + j] = 0.f;
 }
 
-template <int RFMT, bool INSTR, bool MULTI>
-__global__ __launch_bounds__(NT) void k_raster_bwd(
+// TILEM: an instance for GS_REDUCE_TILE alone, without the per-fragment reduction paths of the
+// paper's modes (the instances with TILEM = false take every mode from `mode`).
+template <int RFMT, bool INSTR, bool MULTI, bool TILEM>
+__global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
     const uint2* __restrict__ rect, const int32_t* __restrict__ order,
     const uint32_t* __restrict__ bits, int wpr, int W, int H, int tiles_x,
@@ -1015,7 +1017,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     const uint64_t lt = mask_lt(lane);
     const float cx0 = (float)wx0 + 4.f, cy0 = (float)wy0 + 4.f;   // centre of sub-block 0
     const size_t P = (size_t)W * H;
-    const bool tile_acc = (mode == GS_REDUCE_TILE);
+    const bool tile_acc = TILEM || (mode == GS_REDUCE_TILE);
     int pend = 0;                       // staged entries whose LDS gradients are not yet flushed
     if (tile_acc)
 #pragma unroll
@@ -1056,7 +1058,7 @@ __global__ __launch_bounds__(NT) void k_raster_bwd(
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     BwdCounts cnt = {0, 0, 0, 0, 0, 0};
     uint32_t nq = 0;
-    const bool lane_acc = (mode == GS_REDUCE_HYBRID_LANE || mode == GS_REDUCE_TILE);
+    const bool lane_acc = TILEM || (mode == GS_REDUCE_HYBRID_LANE || mode == GS_REDUCE_TILE);
 
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
     const int nch = (nvis + 63) / 64;
@@ -1495,20 +1497,24 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
               int, int, int, float, float, float, int, const void*, const float*, const float*, int,
               int, float*, float*, int32_t*, unsigned long long*, uint64_t) = nullptr;
-#define GSR_BWD_PICK(IN, MU)                                             \
-    switch (rfmt) {                                                      \
-    case FB_F32: k = k_raster_bwd<FB_F32, IN, MU>; break;                \
-    case FB_F16: k = k_raster_bwd<FB_F16, IN, MU>; break;                \
-    case FB_UNORM16: k = k_raster_bwd<FB_UNORM16, IN, MU>; break;        \
-    case FB_BF16: k = k_raster_bwd<FB_BF16, IN, MU>; break;              \
-    case FB_UNORM8: k = k_raster_bwd<FB_UNORM8, IN, MU>; break;          \
-    default: k = k_raster_bwd<-1, IN, MU>; break;                        \
+#define GSR_BWD_PICK(IN, MU, TM)                                             \
+    switch (rfmt) {                                                          \
+    case FB_F32: k = k_raster_bwd<FB_F32, IN, MU, TM>; break;                \
+    case FB_F16: k = k_raster_bwd<FB_F16, IN, MU, TM>; break;                \
+    case FB_UNORM16: k = k_raster_bwd<FB_UNORM16, IN, MU, TM>; break;        \
+    case FB_BF16: k = k_raster_bwd<FB_BF16, IN, MU, TM>; break;              \
+    case FB_UNORM8: k = k_raster_bwd<FB_UNORM8, IN, MU, TM>; break;          \
+    default: k = k_raster_bwd<-1, IN, MU, TM>; break;                        \
     }
+#define GSR_BWD_PICK2(MU, TM)                                                \
+    if (instr) { GSR_BWD_PICK(true, MU, TM) } else { GSR_BWD_PICK(false, MU, TM) }
+    const bool tm = cfg.reduce_mode == GS_REDUCE_TILE;
     if (V > 1) {
-        if (instr) { GSR_BWD_PICK(true, true) } else { GSR_BWD_PICK(false, true) }
+        if (tm) { GSR_BWD_PICK2(true, true) } else { GSR_BWD_PICK2(true, false) }
     } else {
-        if (instr) { GSR_BWD_PICK(true, false) } else { GSR_BWD_PICK(false, false) }
+        if (tm) { GSR_BWD_PICK2(false, true) } else { GSR_BWD_PICK2(false, false) }
     }
+#undef GSR_BWD_PICK2
 #undef GSR_BWD_PICK
     hipLaunchKernelGGL(k, dim3(nblocks, V), dim3(NT), 0, s, n, n_visible, (const Rec*)r.rec,
                        (const uint2*)r.rect, (const int32_t*)r.bwd_order, (const uint32_t*)r.bits,
