@@ -1105,16 +1105,27 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                     const float al = clamp_alpha(araw, amax);
                     // cullingFlag: splat boundary (alpha < 1/255), then T-Culling (T < 1e-4)
                     const bool live = valid[s] && al >= amin && T[s] >= tmin;
+                    // the fragment's nine gradients: added straight into the lane's sums in the
+                    // tile reduction, else kept for the per-fragment reduction
                     float g[9];
+                    if constexpr (!TILEM) {
 #pragma unroll
-                    for (int j = 0; j < 9; ++j) g[j] = 0.f;
+                        for (int j = 0; j < 9; ++j) g[j] = 0.f;
+                    }
                     if (live) {
                         const float Ti = T[s];
                         const float wt = al * Ti;
                         // Eq. 3: dL/dc = dL/dC alpha T
-                        g[6] = G[s][0] * wt;
-                        g[7] = G[s][1] * wt;
-                        g[8] = G[s][2] * wt;
+                        if constexpr (TILEM) {
+                            acc[6] = fmaf(G[s][0], wt, acc[6]);
+                            acc[7] = fmaf(G[s][1], wt, acc[7]);
+                            acc[8] = fmaf(G[s][2], wt, acc[8]);
+                            acc_live = true;
+                        } else {
+                            g[6] = G[s][0] * wt;
+                            g[7] = G[s][1] * wt;
+                            g[8] = G[s][2] * wt;
+                        }
                         // Eq. 7: dL/dalpha = dL/dC . (c T - C') / (1 - alpha), and the final
                         // transmittance's share
                         const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) + G[s][1] * (cg * Ti - Cp[s][1]) +
@@ -1137,12 +1148,23 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                         if (araw < amax) {
                             const float gq = -0.5f * ga * araw;          // dL/dq
                             const float gm = -2.f * ga * araw * (1.0f / LOG2E);
-                            g[5] = ga * araw * inv_o;               // dalpha/do = exp(-q/2)
-                            g[0] = gm * au;
-                            g[1] = gm * fmaf(A.w, au, B.x * dy);
-                            g[2] = gq * dx * dx;
-                            g[3] = 2.f * gq * dx * dy;
-                            g[4] = gq * dy * dy;
+                            const float gy = fmaf(A.w, au, B.x * dy);
+                            if constexpr (TILEM) {
+                                acc[5] = fmaf(ga * araw, inv_o, acc[5]);   // dalpha/do = exp(-q/2)
+                                acc[0] = fmaf(gm, au, acc[0]);
+                                acc[1] = fmaf(gm, gy, acc[1]);
+                                const float gdx = gq * dx;
+                                acc[2] = fmaf(gdx, dx, acc[2]);
+                                acc[3] = fmaf(2.f * gdx, dy, acc[3]);
+                                acc[4] = fmaf(gq * dy, dy, acc[4]);
+                            } else {
+                                g[5] = ga * araw * inv_o;           // dalpha/do = exp(-q/2)
+                                g[0] = gm * au;
+                                g[1] = gm * gy;
+                                g[2] = gq * dx * dx;
+                                g[3] = 2.f * gq * dx * dy;
+                                g[4] = gq * dy * dy;
+                            }
                         }
                     }
                     if (INSTR) {
@@ -1150,14 +1172,20 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                         cnt.live += live;
                         nlive[s] += live;
                     }
-                    if (lane_acc) {
+                    if constexpr (!TILEM) {
+                        if (lane_acc) {
 #pragma unroll
-                        for (int j = 0; j < 9; ++j) acc[j] += g[j];
-                        acc_live = acc_live || live;
-                    } else {
-                        reduce_commit<INSTR>(g, live, gp, mode, X, lane, cnt);
+                            for (int j = 0; j < 9; ++j) acc[j] += g[j];
+                            acc_live = acc_live || live;
+                        } else {
+                            reduce_commit<INSTR>(g, live, gp, mode, X, lane, cnt);
+                        }
                     }
-                    if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
+                    // sub-blocks whose pixels are all T-culled drop out; checked every fourth
+                    // list entry (a later check only costs a few fragments that the T test
+                    // already rejects)
+                    if ((i & 3) == 3 || i + 1 == nlist)
+                        if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
                 }
                 if (tile_acc) {
                     // the wave's lane sums reduced at once; the first lane of each 16-lane row
