@@ -51,7 +51,7 @@ def _parse():
                     help="skip the low-precision gradient error table")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="write profiles/traffic.json from DIR/{fetch,write,cfetch,cwrite} "
-                         "rocprofv3 databases (no GPU work)")
+                         "rocprofv3 databases and the kernel table from DIR/kt (no GPU work)")
     return ap.parse_args()
 
 
@@ -90,8 +90,8 @@ def format_error_table(g, g_ref):
 
 
 # the launches of the timed raster stages (paper mode, FP16 at rest, no counters)
-FWD_KERNELS = ("k_raster_fwd<-1, false, false>", "k_raster_merge")
-BWD_KERNELS = ("k_raster_bwd<-1, false>",)
+FWD_KERNELS = ("k_raster_fwd<-1, false, false, false>", "k_raster_merge")
+BWD_KERNELS = ("k_raster_bwd<-1, false, false, true>",)
 
 
 def main():
@@ -103,7 +103,10 @@ def main():
     if args.summarize_pmc:
         from paper_2505_18764_amd import pmc
         d = args.summarize_pmc
-        B = "python -u bench.py --steps 3 --warmup 1 --no-cpu --no-tile --serve-requests 0 --formats f16"
+        B = ("python -u bench.py --steps 3 --warmup 1 --no-cpu --no-tile --serve-requests 0 "
+             "--no-format-errors --no-views --formats f16")
+        KT = ("python -u bench.py --steps 5 --warmup 1 --no-cpu --no-tile --serve-requests 0 "
+              "--no-format-errors --no-views --formats f16")
         cmd = "\n".join([
             "cd /tmp && export TMPDIR=/tmp && R=<repository root>",
             f"rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $OUT/fetch -o run -- {B.replace('bench.py', '$R/bench.py')}",
@@ -116,6 +119,14 @@ def main():
                             os.path.join(ROOT, "profiles"), cmd,
                             "1M clustered Gaussians, 1600x1064, FP16 framebuffer")
         print(json.dumps({k: v for k, v in res.items() if k.startswith("_")}))
+        if os.path.isdir(os.path.join(d, "kt")):
+            kcmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $OUT/kt "
+                    f"-o run -- {KT.replace('bench.py', '$R/bench.py')}")
+            pmc.trace_summary(os.path.join(d, "kt"),
+                              os.path.join(ROOT, "profiles", "kernels_1M_1600x1064_f16.md"), kcmd,
+                              "1M clustered Gaussians, 1600x1064, FP16 framebuffer",
+                              note="Seven views: one warmup, one instrumented (the INSTR = true "
+                                   "instances count fragments for the stats), five timed.")
         return
     import torch
     import synth

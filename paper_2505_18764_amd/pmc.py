@@ -9,7 +9,8 @@ two ways: the calibration factor of each counter is bytes copied / (counter KiB 
 ``summarize`` writes ``traffic.json`` (per kernel: scaled bytes read, written, and their sum per
 launch, the mean launch duration, and the hash of the kernel sources the counters were taken
 with; a consumer ignores entries whose hash differs from the current sources) and a short
-markdown table.
+markdown table. ``trace_summary`` turns a ``--kernel-trace --stats`` database into a markdown
+table of kernel durations.
 """
 from __future__ import annotations
 
@@ -111,3 +112,28 @@ def summarize(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes: int,
     with open(os.path.join(out_dir, "traffic_1M_1600x1064_f16.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     return res
+
+
+def trace_summary(path: str, out_md: str, command: str, workload: str, note: str = "") -> list:
+    """Markdown table of kernel durations (calls, total, mean, share) from a rocprofv3
+    ``--kernel-trace`` database; returns the rows."""
+    cur = sqlite3.connect(_db(path)).cursor()
+    rows = list(cur.execute(
+        "select name, total_calls, total_duration, average, percentage from top_kernels"))
+    lines = [f"# Kernel durations: {workload}", "",
+             "Command (on one MI355X; `$R` is the repository root, `$OUT` any scratch directory):",
+             "", "```", command, "```", "",
+             "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+    out = []
+    for n, c, tot, avg, pct in rows:
+        if pct < 0.05:
+            continue
+        k = short_name(n)
+        out.append((k, int(c), tot, avg, pct))       # the view reports microseconds
+        lines.append(f"| `{k}` | {int(c)} | {tot:.1f} | {avg:.1f} | {pct:.1f} |")
+    lines += ["", f"Source hash of the kernels measured: `{source_hash()}`."]
+    if note:
+        lines += ["", note]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out

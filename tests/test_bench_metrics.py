@@ -25,3 +25,13 @@ def test_format_error_table_known_values():
 def test_format_error_table_empty_bins():
     t = bench.format_error_table(np.zeros(3), np.zeros(3))
     assert t["rmse"] == 0.0 and t["mre_10_inf"] is None
+
+
+def test_roofline_kernels_are_in_the_traffic_summary():
+    """The launches bench.py prices its roofline on are named as the committed counters name
+    them (the kernel templates' instances), so the traffic figure can be found."""
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(bench.__file__), "profiles", "traffic.json")))
+    for k in bench.FWD_KERNELS + bench.BWD_KERNELS:
+        assert k in d, k
