@@ -119,6 +119,13 @@ def main():
                             os.path.join(ROOT, "profiles"), cmd,
                             "1M clustered Gaussians, 1600x1064, FP16 framebuffer")
         print(json.dumps({k: v for k, v in res.items() if k.startswith("_")}))
+        if os.path.isdir(os.path.join(d, "sq")):
+            scmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU "
+                    "SQ_INSTS_LDS SQ_WAVES SQ_INSTS_VALU_TRANS_F32 SQ_BUSY_CYCLES --kernel-trace "
+                    f"-d $OUT/sq -o run -- {B.replace('bench.py', '$R/bench.py')}")
+            pmc.issue_summary(os.path.join(d, "sq"),
+                              os.path.join(ROOT, "profiles", "issue_1M_1600x1064_f16.md"), scmd,
+                              "1M clustered Gaussians, 1600x1064, FP16 framebuffer")
         if os.path.isdir(os.path.join(d, "kt")):
             kcmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $OUT/kt "
                     f"-o run -- {KT.replace('bench.py', '$R/bench.py')}")

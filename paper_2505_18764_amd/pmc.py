@@ -10,7 +10,8 @@ two ways: the calibration factor of each counter is bytes copied / (counter KiB 
 launch, the mean launch duration, and the hash of the kernel sources the counters were taken
 with; a consumer ignores entries whose hash differs from the current sources) and a short
 markdown table. ``trace_summary`` turns a ``--kernel-trace --stats`` database into a markdown
-table of kernel durations.
+table of kernel durations; ``issue_summary`` turns an SQ instruction-counter pass into the VALU
+issue share of each kernel.
 """
 from __future__ import annotations
 
@@ -137,3 +138,39 @@ def trace_summary(path: str, out_md: str, command: str, workload: str, note: str
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     return out
+
+
+CLOCK_HZ = 2.4e9          # MI355X peak engine clock
+SIMDS = 256 * 4           # 256 CUs x 4 SIMDs
+VALU_CYCLES = 4           # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+
+
+def issue_summary(path: str, out_md: str, command: str, workload: str, top: int = 8) -> dict:
+    """Per kernel: wave instructions issued per launch (SQ_INSTS_VALU, _SALU, _LDS,
+    _VALU_TRANS_F32) and the VALU issue share = 4 x VALU instructions / (launch duration x
+    clock x 1024 SIMDs), i.e. the fraction of the chip's SIMD cycles the kernel's VALU work
+    fills at the peak clock."""
+    m = counter_means(path)
+    res = {}
+    lines = [f"# Instruction issue per launch: {workload}", "",
+             "Command (on one MI355X; `$R` is the repository root, `$OUT` any scratch directory):",
+             "", "```", command, "```", "",
+             "VALU share = 4 cycles x SQ_INSTS_VALU / (mean launch duration x 2.4 GHz x 1024 SIMDs);",
+             "a value near 1 means the SIMDs issue a VALU instruction almost every cycle.", "",
+             "| kernel | mean us | VALU (M) | trans (M) | SALU (M) | LDS (M) | VALU share |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(m, key=lambda k: -m[k]["_dur_ns"] * m[k]["_calls"])[:top]:
+        v = m[k]
+        if "SQ_INSTS_VALU" not in v:
+            continue
+        dur = v["_dur_ns"] * 1e-9
+        share = VALU_CYCLES * v["SQ_INSTS_VALU"] / (dur * CLOCK_HZ * SIMDS)
+        res[k] = dict(valu=v["SQ_INSTS_VALU"], share=share, mean_ns=v["_dur_ns"])
+        lines.append(f"| `{k}` | {v['_dur_ns'] / 1e3:.1f} | {v['SQ_INSTS_VALU'] / 1e6:.1f} | "
+                     f"{v.get('SQ_INSTS_VALU_TRANS_F32', 0) / 1e6:.1f} | "
+                     f"{v.get('SQ_INSTS_SALU', 0) / 1e6:.1f} | {v.get('SQ_INSTS_LDS', 0) / 1e6:.1f} | "
+                     f"{share:.2f} |")
+    lines += ["", f"Source hash of the kernels measured: `{source_hash()}`."]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return res
