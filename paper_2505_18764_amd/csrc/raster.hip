@@ -39,6 +39,8 @@ constexpr int BATCH = 256;         // splat records staged in LDS at once
 // FP32 conic (products exact, one rounding), k and det Q / a in FP32, and they are stored
 // pre-scaled, a' = -log2(e) a / 2 and d' = -log2(e) det Q / (2a), so that the exponent of
 // alpha = o 2^p is p = a' u^2 + d' dy^2 = -q/2 log2(e), u = dx + k dy.
+// Fields: a = (mean x, mean y, a', k), b = (d', opacity, r, g), c = (b colour, log2 opacity,
+// p_min, sorted position); the forward reads c.x and c.y together.
 struct __align__(16) Rec {
     float4 a;
     float4 b;
@@ -313,7 +315,7 @@ constexpr int MAX_LDS_TILES = 8192;
 constexpr uint32_t NO_TILE_X = 0xFFFFu;         // rect.x of a splat that touches no tile
 
 struct IdRec {
-    Rec r;          // c.y (the sorted position) is filled in by k_raster_setup
+    Rec r;          // c.w (the sorted position) is filled in by k_raster_setup
     uint2 rect;     // tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16)
     uint2 pad;
 };
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(256) void k_raster_pack(
             q.r.b = make_float4(-0.5f * LOG2E * (detf / a), o, cr, cg);
             const float lo = log2f(o);
             const float pmin = log2f(amin) - lo;
-            q.r.c = make_uint4(__float_as_uint(cb), 0u, __float_as_uint(pmin), __float_as_uint(lo));
+            q.r.c = make_uint4(__float_as_uint(cb), __float_as_uint(lo), __float_as_uint(pmin), 0u);
             q.rect = make_uint2((x0 / TILE) | (((x1 - 1) / TILE) << 16),
                                 (y0 / TILE) | (((y1 - 1) / TILE) << 16));
         }
@@ -416,7 +418,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_setup(
         uint2 rr = make_uint2(NO_TILE_X, 0u);
         if (p < n && ids[j] >= 0 && q[j].rect.x != NO_TILE_X) {
             Rec r = q[j].r;
-            r.c.y = (uint32_t)p;
+            r.c.w = (uint32_t)p;
             rec[p] = r;
             rr = q[j].rect;
         }
@@ -490,13 +492,13 @@ __global__ __launch_bounds__(256, 4) void k_raster_setup(
 // the hits are staged into LDS in batches. A dense tile's round is 4096 consecutive splats; a
 // sparse tile skips the chunks none of whose splats touch it, so its walk takes few rounds.
 struct Walk {
+    Rec rec[BATCH];             // first: its reads take small immediate offsets
     uint16_t seg[4][SPAN];      // per wave: hits as chunk slot << 6 | lane
     uint16_t list[4][BATCH];
     int chunk[64];              // the round's chunks, increasing
     int nchunk;
     int segn[4];
     int alive[4];
-    Rec rec[BATCH];
 };
 
 // alpha = o exp(-q/2) = exp2(log2 o + p) with p = a' u^2 + d' dy^2, u = dx + k dy (the record's
@@ -652,7 +654,7 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
         const uint32_t v = w.seg[ws][off];
         const int pos = w.chunk[v >> 6] * 64 + (int)(v & 63u);
         Rec r = rec[pos];
-        r.c.y = (uint32_t)pos;      // the gradient slot comes from the walk, never from memory
+        r.c.w = (uint32_t)pos;      // the gradient slot comes from the walk, never from memory
         w.rec[tid] = r;
     }
 }
@@ -760,7 +762,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                     const float cb = __uint_as_float(Cw.x);
                     // the exponent's row part (log2 o folded in) for the lane's two pixel rows
                     float dxs[2], dys[2], er[2];
-                    alpha_rows(A, B, __uint_as_float(Cw.w), px, py, dxs, dys, er);
+                    alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
                         if (((ent >> (8 + s)) & 1u) && (!TCULL || ((alive >> s) & 1u))) {
@@ -969,7 +971,7 @@ __device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Wa
 #pragma unroll
         for (int j = 0; j < 9; ++j) { v[j] = tg[tid * 9 + j]; any = any || v[j] != 0.f; }
         if (any) {
-            float* gp = grad + (size_t)w.rec[tid].c.y * GRAD_STRIDE;
+            float* gp = grad + (size_t)w.rec[tid].c.w * GRAD_STRIDE;
 #pragma unroll
             for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, v[j]);
             if (INSTR) cnt.sets += 1;
@@ -1086,9 +1088,9 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                 const float4 B = w.rec[k].b;
                 const uint4 Cw = w.rec[k].c;
                 const float cr = B.z, cg = B.w, cb = __uint_as_float(Cw.x);
-                float* gp = grad + (size_t)uniform(Cw.y) * GRAD_STRIDE;
+                float* gp = grad + (size_t)uniform(Cw.w) * GRAD_STRIDE;
                 float dxs[2], dys[2], er[2];
-                alpha_rows(A, B, __uint_as_float(Cw.w), px, py, dxs, dys, er);
+                alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
                 const float inv_o = __builtin_amdgcn_rcpf(B.y);
                 float acc[9];
 #pragma unroll
