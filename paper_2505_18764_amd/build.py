@@ -1,7 +1,8 @@
 """Build libgsr.so (all HIP sources for gfx950) in-tree with hipcc.
 
 Each source is compiled to an object in parallel, then linked into one shared library next to
-this file. Packed-FP32 instruction selection is disabled for every HIP source.
+this file. Packed-FP32 instruction selection is disabled for every HIP source, and so is the
+compiler's atomic optimizer.
 """
 from __future__ import annotations
 
@@ -20,6 +21,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # atomics stay as written: the kernels already reduce before their atomics, and the
+         # compiler's lane-combining loop around a single lane's LDS add only costs instructions
+         "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster.hip", "tile.hip"]
 

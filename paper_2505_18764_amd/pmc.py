@@ -26,12 +26,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def source_hash() -> str:
-    """Hash of the HIP sources (the counters describe the kernels these sources build)."""
+    """Hash of the HIP sources and the build flags (the counters describe the kernels these
+    build)."""
     h = hashlib.sha256()
     d = os.path.join(HERE, "csrc")
     for f in sorted(os.listdir(d)):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
+    from .build import FLAGS
+    h.update(" ".join(FLAGS).encode())
     return h.hexdigest()[:16]
 
 
