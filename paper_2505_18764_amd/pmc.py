@@ -33,8 +33,11 @@ def source_hash() -> str:
     for f in sorted(os.listdir(d)):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
-    from .build import FLAGS
-    h.update(" ".join(FLAGS).encode())
+    from .build import FLAGS, SOURCE_FLAGS
+    flags = [f for i, f in enumerate(FLAGS) if f != "-I" and (i == 0 or FLAGS[i - 1] != "-I")]
+    h.update(" ".join(flags).encode())              # no paths: the hash is the same on any host
+    for src in sorted(SOURCE_FLAGS):
+        h.update((src + " " + " ".join(SOURCE_FLAGS[src])).encode())
     return h.hexdigest()[:16]
 
 
