@@ -299,18 +299,19 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // Two kernels. k_raster_pack runs in splat-id order: it reads the caller's arrays coalesced and
 // writes each splat's record fields and tile rectangle as one 64-byte IdRec. k_raster_setup runs
 // in sorted order: one workgroup per SETUP_SPAN consecutive sorted positions = one 32-bit column
-// of the bitmap (32 chunks of 64 splats); each thread gathers its eight splats' IdRecs by id (one
-// cache line each, all eight in flight), writes the sorted records, and the workgroup gathers, in
-// LDS, one word of chunk bits and one splat count per tile, then writes its bitmap column with
-// plain stores and adds its counts to the tile weights: one global atomic per (workgroup, touched
-// tile), none contended within an instruction. The LDS arrays are sized to the image's tiles at
+// of the bitmap (32 chunks of 64 splats); each of its 1024 threads gathers its two splats' IdRecs
+// by id (one cache line each, both in flight), writes the sorted records, and the workgroup
+// gathers, in LDS, one word of chunk bits and one splat count per tile, then writes its bitmap
+// column with plain stores and adds its counts to the tile weights: one global atomic per
+// (workgroup, touched tile), none contended within an instruction. The LDS arrays are sized to the image's tiles at
 // launch (8 B per tile), so that several workgroups share a CU. The (splat, tile) pairs of each
-// round of 256 splats are spread evenly over the threads: a scan of the splats' pair counts gives
+// round of 1024 splats are spread evenly over the threads: a scan of the splats' pair counts gives
 // each thread an equal run of consecutive pairs, whose first owner a binary search finds; the
 // thread then walks the run tile by tile. One splat may cover every tile of the image, and a
 // thread walking its own splats' tiles would leave the workgroup waiting on it.
 constexpr int SETUP_SPAN = 32 * CHUNK_SPLATS;   // 2048 sorted positions per workgroup
-constexpr int SETUP_PER_THREAD = SETUP_SPAN / 256;
+constexpr int SETUP_NT = 1024;                  // threads: 16 waves keep the gathers in flight
+constexpr int SETUP_PER_THREAD = SETUP_SPAN / SETUP_NT;
 constexpr int MAX_LDS_TILES = 8192;
 constexpr uint32_t NO_TILE_X = 0xFFFFu;         // rect.x of a splat that touches no tile
 
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(256) void k_raster_pack(
     out[id] = q;
 }
 
-__global__ __launch_bounds__(256, 4) void k_raster_setup(
+__global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
     int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
     const IdRec* __restrict__ idrec, int tiles_x, int ntiles, Rec* __restrict__ rec,
     uint2* __restrict__ rect, int32_t* __restrict__ inv, uint32_t* __restrict__ weights,
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_setup(
     int ids[SETUP_PER_THREAD];
 #pragma unroll
     for (int j = 0; j < SETUP_PER_THREAD; ++j) {
-        const int p = p0 + j * 256 + threadIdx.x;
+        const int p = p0 + j * SETUP_NT + threadIdx.x;
         const int id = p < n ? sorted_ids[p] : -1;
         if ((unsigned)id < (unsigned)n) inv[id] = p;    // sorted position by id, for the backward
         ids[j] = (p < nvis && (unsigned)id < (unsigned)n) ? id : -1;
@@ -409,12 +410,12 @@ __global__ __launch_bounds__(256, 4) void k_raster_setup(
 #pragma unroll
     for (int j = 0; j < SETUP_PER_THREAD; ++j)
         if (ids[j] >= 0) q[j] = idrec[ids[j]];
-    __shared__ uint32_t s_first[257];      // exclusive scan of the round's pair counts
-    __shared__ uint2 s_rect[256];
-    __shared__ uint32_t s_wtot[4];
+    __shared__ uint32_t s_first[SETUP_NT + 1];   // exclusive scan of the round's pair counts
+    __shared__ uint2 s_rect[SETUP_NT];
+    __shared__ uint32_t s_wtot[SETUP_NT / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int j = 0; j < SETUP_PER_THREAD; ++j) {
-        const int p = p0 + j * 256 + tid;
+        const int p = p0 + j * SETUP_NT + tid;
         uint2 rr = make_uint2(NO_TILE_X, 0u);
         if (p < n && ids[j] >= 0 && q[j].rect.x != NO_TILE_X) {
             Rec r = q[j].r;
@@ -445,15 +446,15 @@ __global__ __launch_bounds__(256, 4) void k_raster_setup(
         for (int w2 = 0; w2 < wave; ++w2) before += s_wtot[w2];
         s_first[tid] = before + incl - cnt;
         s_rect[tid] = rr;
-        if (tid == 255) s_first[256] = before + incl;
+        if (tid == SETUP_NT - 1) s_first[SETUP_NT] = before + incl;
         __syncthreads();
-        const uint32_t total = s_first[256];
-        const uint32_t per = (total + 255u) / 256u;
+        const uint32_t total = s_first[SETUP_NT];
+        const uint32_t per = (total + SETUP_NT - 1u) / SETUP_NT;
         const uint32_t k0 = min((uint32_t)tid * per, total), k1 = min(k0 + per, total);
         if (k0 < k1) {
             int i = 0;                     // owner of pair k0: the last entry whose first pair <= k0
 #pragma unroll
-            for (int step = 128; step > 0; step >>= 1)
+            for (int step = SETUP_NT / 2; step > 0; step >>= 1)
                 if (s_first[i + step] <= k0) i += step;
             uint2 ro = s_rect[i];
             uint32_t w = (ro.x >> 16) - (ro.x & 0xFFFFu) + 1u;
@@ -470,7 +471,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_setup(
                     ty = ro.y & 0xFFFFu;
                 }
                 const uint32_t t = ty * (uint32_t)tiles_x + tx;
-                atomicOr(&s_bits[t], 1u << (j * (256 / CHUNK_SPLATS) + i / CHUNK_SPLATS));
+                atomicOr(&s_bits[t], 1u << (j * (SETUP_NT / CHUNK_SPLATS) + i / CHUNK_SPLATS));
                 atomicAdd(&s_cnt[t], 1u);
                 if (++tx > (ro.x >> 16)) { tx = ro.x & 0xFFFFu; ++ty; }
             }
@@ -1405,8 +1406,8 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
                            conics, opac, rgb, width, height, cfg.alpha_min, sat, (IdRec*)r.idrec,
                            vs.ws);
         const size_t lds = ntiles <= MAX_LDS_TILES ? (size_t)ntiles * 8 : 0;
-        hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V), dim3(256),
-                           lds, s, n, sorted_ids, n_visible, (const IdRec*)r.idrec, tiles_x, ntiles,
+        hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V),
+                           dim3(SETUP_NT), lds, s, n, sorted_ids, n_visible, (const IdRec*)r.idrec, tiles_x, ntiles,
                            (Rec*)r.rec, (uint2*)r.rect, r.inv, r.weights, r.bits, r.wpr, r.colcnt,
                            vs.ws);
     }
