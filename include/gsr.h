@@ -141,7 +141,11 @@ typedef struct gs_stats {
     unsigned long long bwd_wave_reductions;
     unsigned long long bwd_quad_reductions;
     unsigned long long bwd_cohesive;    /* reductions whose live lanes all held one splat */
-    unsigned long long reserved[6];
+    unsigned long long fwd_walked;      /* (wave, splat) entries of the forward's culled lists */
+    unsigned long long fwd_empty_blocks;/* (8x8 sub-block, splat) evaluations where no alpha passed */
+    unsigned long long fwd_chunks;      /* (tile, 16-splat chunk) pairs whose rectangles were tested */
+    unsigned long long fwd_batches;     /* staged batches of up to 256 records */
+    unsigned long long reserved[2];
 } gs_stats;
 
 /* Workspace users (argument `op` of gs_workspace_size). */
@@ -239,7 +243,7 @@ int gs_sort_views(int32_t n_views, int32_t n, uint32_t* keys, int32_t* ids,
 /*
  * Raster setup, shared by the forward and the backward walk: per sorted position, the splat's
  * record (mean, conic factors, opacity, colour, pixel bounding box of the alpha >= alpha_min
- * ellipse) and its tile rectangle; per tile, an occupancy bitmap over chunks of 64 sorted splats
+ * ellipse) and its tile rectangle; per tile, an occupancy bitmap over chunks of 16 sorted splats
  * and a splat count that orders the tiles heaviest first. gs_raster_fwd and gs_raster_bwd run it
  * themselves unless cfg->flags has GS_FLAG_REUSE_SETUP; calling it once and passing that flag to
  * both lets one view's forward and backward share it. The setup depends on the inputs, the image

@@ -52,11 +52,11 @@ def camera_array(cams) -> ctypes.Array:
 
 STATS_FIELDS = ["fwd_queued", "fwd_evaluated", "fwd_covered", "bwd_queued", "bwd_evaluated",
                 "bwd_live", "bwd_atomic_sets", "bwd_wave_reductions", "bwd_quad_reductions",
-                "bwd_cohesive"]
+                "bwd_cohesive", "fwd_walked", "fwd_empty_blocks", "fwd_chunks", "fwd_batches"]
 
 
 class GsStats(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_ulonglong) for f in STATS_FIELDS] + [("reserved", ctypes.c_ulonglong * 6)]
+    _fields_ = [(f, ctypes.c_ulonglong) for f in STATS_FIELDS] + [("reserved", ctypes.c_ulonglong * 2)]
 
 
 class GsrError(RuntimeError):

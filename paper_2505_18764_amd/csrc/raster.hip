@@ -17,13 +17,14 @@
 //     of its sub-blocks, with a mask of those sub-blocks.
 // Each iteration therefore processes one splat per wave across up to 64 lanes; that is the
 // "subgroup" of Procedure 2, and its live lanes always share one splat id (cohesion 100 %).
+#include <type_traits>
+
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace gsr {
 
 constexpr int NT = 256;            // threads per workgroup
-constexpr int SPAN = 1024;         // hits one wave can hold per round (16 chunks of 64 splats)
 constexpr int BATCH = 256;         // splat records staged in LDS at once
 
 // A staged splat: a = (mean x, mean y, a', k); b = (d', opacity, r, g);
@@ -50,8 +51,14 @@ static_assert(sizeof(Rec) == REC_BYTES, "record size");
 
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr int WEIGHT_SAMPLE = 8;        // every 8th sorted splat votes for the tiles it touches
-constexpr int CHUNK_SPLATS = 64;        // sorted splats per bit of the tile occupancy bitmap
-constexpr size_t BITMAP_BUDGET = 256u << 20;  // the bitmap is skipped above this many bytes
+constexpr int CHUNK_SPLATS = 16;        // sorted splats per bit of the tile occupancy bitmap
+// Occupied chunks a walk round takes. The forward walks every splat of a tile, so its rounds are
+// large (fewer rounds, fuller staged batches); the backward stops where its pixels saturate, and
+// a smaller round stages fewer splats past that point.
+constexpr int ROUND_CHUNKS = 192;
+constexpr int BWD_ROUND_CHUNKS = 64;
+constexpr int SPAN = ROUND_CHUNKS / 4 * CHUNK_SPLATS;   // hits one wave can hold per round
+constexpr size_t BITMAP_BUDGET = 1024u << 20;  // the bitmap is skipped above this many bytes
 
 // ---- schedule ------------------------------------------------------------------------------
 // The work of a tile grows with the number of splats over it, which on clustered scenes varies
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
 // writing the framebuffer directly (slot -1); otherwise the column counts are scanned and cut
 // where the running count first reaches j w_t / k_t.
 __global__ __launch_bounds__(64) void k_plan_cuts(
-    const uint32_t* __restrict__ weights, const uint16_t* __restrict__ colcnt, int wpr, int ntiles,
+    const uint32_t* __restrict__ weights, const uint16_t* __restrict__ colcnt, int ncol, int ntiles,
     const int32_t* __restrict__ tile_k, const int32_t* __restrict__ tile_first,
     int4* __restrict__ items, uint32_t* __restrict__ item_w, uint64_t vws) {
     weights = view_bytes(weights, vws);
@@ -200,23 +207,23 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
     const uint32_t w = weights[t];
     if (k < 1 || f < 0 || f + k > ITEMS_PER_TILE * ntiles) return;
     if (k == 1) {
-        if (lane == 0) { items[f] = make_int4(t, 0, wpr, -1); item_w[f] = w; }
+        if (lane == 0) { items[f] = make_int4(t, 0, ncol, -1); item_w[f] = w; }
         return;
     }
     __shared__ int cut[MAX_SEGMENTS + 1];            // in LDS: indexed by a runtime j below
     __shared__ uint32_t cum[MAX_SEGMENTS + 1];
     __shared__ uint32_t tgt[MAX_SEGMENTS];           // cut j where the count first reaches tgt[j]
-    if (lane <= MAX_SEGMENTS) { cut[lane] = lane ? wpr : 0; cum[lane] = lane ? w : 0u; }
+    if (lane <= MAX_SEGMENTS) { cut[lane] = lane ? ncol : 0; cum[lane] = lane ? w : 0u; }
     if (lane < MAX_SEGMENTS) tgt[lane] = (uint32_t)(((unsigned long long)w * lane + k - 1) / k);
     __syncthreads();
     int found = 1;                                   // next cut to find
     uint32_t base = 0u;
-    const uint16_t* row = colcnt + (size_t)t * wpr;
+    const uint16_t* row = colcnt + (size_t)t * ncol;
     // the first PRE chunks of 64 columns are loaded together, later ones one at a time
     constexpr int PRE = 16;
     uint32_t pre[PRE];
 #pragma unroll
-    for (int i = 0; i < PRE; ++i) pre[i] = (i * 64 + lane < wpr) ? row[i * 64 + lane] : 0u;
+    for (int i = 0; i < PRE; ++i) pre[i] = (i * 64 + lane < ncol) ? row[i * 64 + lane] : 0u;
     auto chunk = [&](int c0, uint32_t v) {
         for (int o = 1; o < 64; o <<= 1) {          // inclusive prefix over the wave
             const uint32_t u = __shfl_up(v, o);
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
         }
         const uint32_t incl = base + v;
         for (int j = found; j < k; ++j) {
-            const uint64_t m = ballot(incl >= tgt[j] && c0 + lane < wpr);
+            const uint64_t m = ballot(incl >= tgt[j] && c0 + lane < ncol);
             if (!m) break;                          // later targets are larger still
             const int l = __builtin_ctzll(m);
             if (lane == l) { cut[j] = c0 + l + 1; cum[j] = incl; }
@@ -234,12 +241,12 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
     };
 #pragma unroll
     for (int i = 0; i < PRE; ++i)
-        if (i * 64 < wpr && found < k) chunk(i * 64, pre[i]);
-    for (int c0 = PRE * 64; c0 < wpr && found < k; c0 += 64)
-        chunk(c0, (c0 + lane < wpr) ? row[c0 + lane] : 0u);
+        if (i * 64 < ncol && found < k) chunk(i * 64, pre[i]);
+    for (int c0 = PRE * 64; c0 < ncol && found < k; c0 += 64)
+        chunk(c0, (c0 + lane < ncol) ? row[c0 + lane] : 0u);
     __syncthreads();
     if (lane == 0) {
-        cut[k] = wpr; cum[k] = w;
+        cut[k] = ncol; cum[k] = w;
         for (int j = 0; j < k; ++j) {
             const int a = cut[j], b = max(cut[j], cut[j + 1]);
             items[f + j] = make_int4(t, a, b, f + j);
@@ -298,20 +305,24 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // ---- setup: records, tile rectangles, occupancy bitmap and tile weights ---------------------
 // Two kernels. k_raster_pack runs in splat-id order: it reads the caller's arrays coalesced and
 // writes each splat's record fields and tile rectangle as one 64-byte IdRec. k_raster_setup runs
-// in sorted order: one workgroup per SETUP_SPAN consecutive sorted positions = one 32-bit column
-// of the bitmap (32 chunks of 64 splats); each of its 1024 threads gathers its two splats' IdRecs
-// by id (one cache line each, both in flight), writes the sorted records, and the workgroup
-// gathers, in LDS, one word of chunk bits and one splat count per tile, then writes its bitmap
-// column with plain stores and adds its counts to the tile weights: one global atomic per
-// (workgroup, touched tile), none contended within an instruction. The LDS arrays are sized to the image's tiles at
-// launch (8 B per tile), so that several workgroups share a CU. The (splat, tile) pairs of each
-// round of 1024 splats are spread evenly over the threads: a scan of the splats' pair counts gives
-// each thread an equal run of consecutive pairs, whose first owner a binary search finds; the
-// thread then walks the run tile by tile. One splat may cover every tile of the image, and a
-// thread walking its own splats' tiles would leave the workgroup waiting on it.
-constexpr int SETUP_SPAN = 32 * CHUNK_SPLATS;   // 2048 sorted positions per workgroup
+// in sorted order: one workgroup per SETUP_SPAN consecutive sorted positions = one column of
+// the bitmap (COL_WORDS words, 128 chunks of 16 splats); each of its 1024 threads gathers its two
+// splats' IdRecs by id (one cache line each, both in flight), writes the sorted records, and the
+// workgroup gathers, in LDS, the column's chunk bits and a 16-bit splat count per tile, then
+// writes its bitmap column with plain stores and adds its counts to the tile weights: one global
+// atomic per (workgroup, touched tile), none contended within an instruction. The LDS arrays are
+// sized to the image's tiles at launch (18 B per tile). The (splat, tile) pairs of each round of
+// 1024 splats are spread evenly over the threads: a scan of the splats' pair counts gives each
+// thread an equal run of consecutive pairs, whose first owner a binary search finds; the thread
+// then walks the run tile by tile. One splat may cover every tile of the image, and a thread
+// walking its own splats' tiles would leave the workgroup waiting on it.
+constexpr int SETUP_SPAN = 2048;                // sorted positions per workgroup = one column
 constexpr int SETUP_NT = 1024;                  // threads: 16 waves keep the gathers in flight
 constexpr int SETUP_PER_THREAD = SETUP_SPAN / SETUP_NT;
+constexpr int COL_CHUNKS = SETUP_SPAN / CHUNK_SPLATS;   // 128 chunks per column
+constexpr int COL_WORDS = COL_CHUNKS / 32;              // 4 bitmap words per (tile, column)
+static_assert(COL_WORDS == 4, "a column of a tile's bitmap row is stored as one uint4");
+// 18 B of LDS per tile (4 words of bits, a 16-bit count) and 12.1 KB of fixed arrays in 160 KB
 constexpr int MAX_LDS_TILES = 8192;
 constexpr uint32_t NO_TILE_X = 0xFFFFu;         // rect.x of a splat that touches no tile
 
@@ -379,9 +390,11 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
     const IdRec* __restrict__ idrec, int tiles_x, int ntiles, Rec* __restrict__ rec,
     uint2* __restrict__ rect, int32_t* __restrict__ inv, uint32_t* __restrict__ weights,
     uint32_t* __restrict__ bits, int wpr, uint16_t* __restrict__ colcnt, uint64_t vws) {
-    extern __shared__ uint32_t s_dyn[];   // [2][ntiles] when ntiles <= MAX_LDS_TILES
+    // when ntiles <= MAX_LDS_TILES: [ntiles][COL_WORDS] chunk bits, then the tiles' 16-bit
+    // counts two to a word (a count is at most SETUP_SPAN, so an add never carries across)
+    extern __shared__ uint32_t s_dyn[];
     uint32_t* s_bits = s_dyn;
-    uint32_t* s_cnt = s_dyn + ntiles;
+    uint32_t* s_cnt = s_dyn + (size_t)ntiles * COL_WORDS;
     sorted_ids = view_at(sorted_ids, (uint64_t)n);
     nvis_ptr = view_at(nvis_ptr, 1);
     idrec = view_bytes(idrec, vws);
@@ -392,8 +405,10 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
     bits = view_bytes(bits, vws);
     colcnt = view_bytes(colcnt, vws);
     const bool in_lds = ntiles <= MAX_LDS_TILES;
+    const int ncol = wpr / COL_WORDS;
     if (in_lds)
-        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) { s_bits[t] = 0u; s_cnt[t] = 0u; }
+        for (int t = threadIdx.x; t < ntiles * COL_WORDS + (ntiles + 1) / 2; t += blockDim.x)
+            s_dyn[t] = 0u;
     __syncthreads();
     int nvis = *nvis_ptr;
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
@@ -471,8 +486,9 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
                     ty = ro.y & 0xFFFFu;
                 }
                 const uint32_t t = ty * (uint32_t)tiles_x + tx;
-                atomicOr(&s_bits[t], 1u << (j * (SETUP_NT / CHUNK_SPLATS) + i / CHUNK_SPLATS));
-                atomicAdd(&s_cnt[t], 1u);
+                const uint32_t c = (uint32_t)(j * SETUP_NT + i) / CHUNK_SPLATS;   // < COL_CHUNKS
+                atomicOr(&s_bits[t * COL_WORDS + (c >> 5)], 1u << (c & 31u));
+                atomicAdd(&s_cnt[t >> 1], 1u << ((t & 1u) << 4));
                 if (++tx > (ro.x >> 16)) { tx = ro.x & 0xFFFFu; ++ty; }
             }
         }
@@ -480,23 +496,30 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
     }
     if (in_lds)
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-            if (wpr > 0) bits[(size_t)t * wpr + blockIdx.x] = s_bits[t];
-            if (colcnt) colcnt[(size_t)t * wpr + blockIdx.x] = (uint16_t)s_cnt[t];   // <= 2048
-            if (s_cnt[t]) atomicAdd(&weights[t], s_cnt[t]);
+            const uint32_t cnt = (s_cnt[t >> 1] >> ((t & 1) << 4)) & 0xFFFFu;
+            if (wpr > 0) {
+                const uint32_t* sb = s_bits + (size_t)t * COL_WORDS;
+                reinterpret_cast<uint4*>(bits + (size_t)t * wpr)[blockIdx.x] =
+                    make_uint4(sb[0], sb[1], sb[2], sb[3]);
+            }
+            if (colcnt) colcnt[(size_t)t * ncol + blockIdx.x] = (uint16_t)cnt;
+            if (cnt) atomicAdd(&weights[t], cnt);
         }
 }
 
 // ---- the shared walk ------------------------------------------------------------------------
-// Rounds of up to 64 occupied chunks (chunk = 64 consecutive sorted splats; occupied = its bit is
+// Rounds of up to RC occupied chunks (chunk = 16 consecutive sorted splats; occupied = its bit is
 // set in the tile's occupancy bitmap). Wave w tests the splats of the round's chunks
-// [16 w, 16 w + 16) against the tile, so the four waves' hit lists concatenate in sorted order;
-// the hits are staged into LDS in batches. A dense tile's round is 4096 consecutive splats; a
-// sparse tile skips the chunks none of whose splats touch it, so its walk takes few rounds.
+// [RC/4 w, RC/4 (w + 1)) against the tile, so the four waves' hit lists concatenate in sorted
+// order; the hits are staged into LDS in batches. A dense tile's round is 16 RC splats; a
+// sparse tile skips the chunks none of whose splats touch it. Most (tile, splat) pairs are
+// sparse: a tile's splats lie far apart in depth order, so an occupied chunk holds one or two
+// hits, and the chunk size sets how many rectangles the walk tests per hit.
 struct Walk {
     Rec rec[BATCH];             // first: its reads take small immediate offsets
-    uint16_t seg[4][SPAN];      // per wave: hits as chunk slot << 6 | lane
+    uint16_t seg[4][SPAN];      // per wave: hits as chunk slot * CHUNK_SPLATS + splat
     uint16_t list[4][BATCH];
-    int chunk[64];              // the round's chunks, increasing
+    int chunk[ROUND_CHUNKS];    // the round's chunks, increasing
     int nchunk;
     int segn[4];
     int alive[4];
@@ -567,18 +590,20 @@ __device__ __forceinline__ int cull_batch(Walk& w, int m, int wave, int lane, ui
     return cnt;
 }
 
-// Wave 0: the next (up to) 64 occupied chunks in [cursor, cend) into w.chunk / w.nchunk, and the
+// Wave 0: the next (up to) RC occupied chunks in [cursor, cend) into w.chunk / w.nchunk, and the
 // cursor moved past them (every chunk counts as occupied without a bitmap). One bitmap word per
 // lane; a wave prefix sum of the words' popcounts places each lane's chunks.
+template <int RC>
 __device__ __forceinline__ void next_round(Walk& w, const uint32_t* __restrict__ trow, int cend,
                                            int lane, int& cursor) {
+    static_assert(RC <= ROUND_CHUNKS, "w.chunk holds ROUND_CHUNKS");
     int cc = cursor, got = 0;
     if (!trow) {
-        got = min(64, max(0, cend - cc));
-        if (lane < got) w.chunk[lane] = cc + lane;
+        got = min(RC, max(0, cend - cc));
+        for (int l = lane; l < got; l += 64) w.chunk[l] = cc + l;
         cc += got;
     } else {
-        while (got < 64 && cc < cend) {
+        while (got < RC && cc < cend) {
             const int wi = (cc >> 5) + lane;
             uint32_t word = wi * 32 < cend ? trow[wi] : 0u;
             if (lane == 0) word &= ~0u << (cc & 31);           // chunks before the cursor
@@ -590,7 +615,7 @@ __device__ __forceinline__ void next_round(Walk& w, const uint32_t* __restrict__
                 const int u = __shfl_up(incl, o);
                 if (lane >= o) incl += u;
             }
-            const int excl = incl - pc, need = 64 - got;
+            const int excl = incl - pc, need = RC - got;
             const int take = max(0, min(pc, need - excl));
             int last = -1;
             for (int t = 0; t < take; ++t) {
@@ -603,7 +628,7 @@ __device__ __forceinline__ void next_round(Walk& w, const uint32_t* __restrict__
             if (total >= need) {                              // the round is full
                 const uint64_t edge = ballot(excl < need && incl >= need);
                 cc = __shfl(last, (int)__builtin_ctzll(edge)) + 1;
-                got = 64;
+                got = RC;
             } else {
                 got += total;
                 cc = ((cc >> 5) + 64) * 32;                    // all 64 words consumed
@@ -614,26 +639,32 @@ __device__ __forceinline__ void next_round(Walk& w, const uint32_t* __restrict__
     if (lane == 0) w.nchunk = got;
 }
 
-// Wave `wave`: tests the splats of the round's chunk slots [16 wave, 16 wave + 16) against the
-// tile; writes the in-order hits to w.seg[wave] (slot << 6 | lane) and their count to w.segn.
+// Wave `wave`: tests the splats of the round's chunk slots [RC/4 wave, RC/4 (wave + 1)) against
+// the tile, four chunks per step (lane = 16 x slot offset + splat), two steps' loads in flight;
+// writes the in-order hits to w.seg[wave] (slot * CHUNK_SPLATS + splat) and their count to
+// w.segn.
+template <int RC>
 __device__ __forceinline__ void scan_round(Walk& w, const uint2* __restrict__ rect, int nvis,
                                            uint32_t ttx, uint32_t tty, int wave, int lane,
                                            uint64_t lt) {
+    constexpr int PER_STEP = 64 / CHUNK_SPLATS, WAVE_CHUNKS = RC / 4;
+    static_assert(WAVE_CHUNKS * CHUNK_SPLATS <= SPAN, "w.seg holds SPAN hits per wave");
     int cnt = 0;
-    const int s0 = wave * 16, s1 = min(w.nchunk, s0 + 16);
-    for (int sl = s0; sl < s1; sl += 2) {                     // two chunks per step
-        const bool two = sl + 1 < s1;
-        const int o0 = w.chunk[sl] * 64 + lane;
-        const int o1 = two ? w.chunk[sl + 1] * 64 + lane : nvis;
+    const int s0 = wave * WAVE_CHUNKS, s1 = min(w.nchunk, s0 + WAVE_CHUNKS);
+    const int sub = lane / CHUNK_SPLATS, idx = lane % CHUNK_SPLATS;
+    for (int sl = s0; sl < s1; sl += 2 * PER_STEP) {
+        const int sa = sl + sub, sb = sl + PER_STEP + sub;
+        const int o0 = sa < s1 ? w.chunk[sa] * CHUNK_SPLATS + idx : nvis;
+        const int o1 = sb < s1 ? w.chunk[sb] * CHUNK_SPLATS + idx : nvis;
         const uint2 r0 = o0 < nvis ? rect[o0] : make_uint2(0xFFFFu, 0u);
         const uint2 r1 = o1 < nvis ? rect[o1] : make_uint2(0xFFFFu, 0u);
         const bool h0 = rect_hit(r0, ttx, tty);
         const uint64_t m0 = ballot(h0);
-        if (h0) w.seg[wave][cnt + popc(m0 & lt)] = (uint16_t)((sl << 6) | lane);
+        if (h0) w.seg[wave][cnt + popc(m0 & lt)] = (uint16_t)(sa * CHUNK_SPLATS + idx);
         cnt += popc(m0);
         const bool h1 = rect_hit(r1, ttx, tty);
         const uint64_t m1 = ballot(h1);
-        if (h1) w.seg[wave][cnt + popc(m1 & lt)] = (uint16_t)(((sl + 1) << 6) | lane);
+        if (h1) w.seg[wave][cnt + popc(m1 & lt)] = (uint16_t)(sb * CHUNK_SPLATS + idx);
         cnt += popc(m1);
     }
     if (lane == 0) w.segn[wave] = cnt;
@@ -653,7 +684,7 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
             }
         }
         const uint32_t v = w.seg[ws][off];
-        const int pos = w.chunk[v >> 6] * 64 + (int)(v & 63u);
+        const int pos = w.chunk[v / CHUNK_SPLATS] * CHUNK_SPLATS + (int)(v % CHUNK_SPLATS);
         Rec r = rec[pos];
         r.c.w = (uint32_t)pos;      // the gradient slot comes from the walk, never from memory
         w.rec[tid] = r;
@@ -661,10 +692,20 @@ __device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int 
 }
 
 // ---- forward -------------------------------------------------------------------------------
+// A half-precision value in a 32-bit slot of its own: arrays of these are not packed two to a
+// register, which would cost a merge after every half-word update.
+struct Half32 {
+    _Float16 h;
+    uint16_t pad;
+    __device__ Half32() = default;
+    __device__ Half32(float x) : h((_Float16)x) {}
+    __device__ explicit operator float() const { return (float)h; }
+};
+
 // One workgroup per work item: a whole tile (items == nullptr: block b takes tile order[b]) or,
 // in the depth-split forward, one depth segment of a tile (columns [c_begin, c_end) of 2048
 // sorted positions), which writes its FP32 (C, T) to partial[slot] instead of the framebuffer.
-// Occupancy: LDS (22.8 KB per workgroup) allows 7 workgroups per CU; the second bound asks the
+// Occupancy: LDS (21.3 KB per workgroup) allows 7 workgroups per CU; the second bound asks the
 // compiler for 7 waves per SIMD (<= 72 VGPRs), which measured faster than 6 with fewer spills.
 // MULTI: a launch over several views (grid y). Its per-view pointers cost scalar registers that
 // the one-view instances, whose walk pointers stay plain kernel arguments, do not pay.
@@ -690,7 +731,8 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         items = view_bytes(items, vws);
         item_order = view_bytes(item_order, vws);
     }
-    int tile, c_begin = 0, c_end = wpr, slot = -1;
+    const int ncol = wpr / COL_WORDS;               // columns of SETUP_SPAN sorted positions
+    int tile, c_begin = 0, c_end = ncol, slot = -1;
     if (items) {
         const int it = item_order[blockIdx.x];
         if (it < 0 || it >= ITEMS_PER_TILE * ntiles) return;      // past the item count
@@ -710,7 +752,12 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     const uint64_t lt = mask_lt(lane);
     const float cx0 = (float)wx0 + 4.f, cy0 = (float)wy0 + 4.f;   // centre of sub-block 0
 
-    float px[4], py[4], C[4][3], T[4];
+    // The running (C, T) as the framebuffer holds it. A half-precision framebuffer's state stays
+    // in half registers: the blend's mixed-precision FMAs read it and round their results to it
+    // directly, with no widening after every update.
+    using St = typename std::conditional<RFMT == FB_F16, Half32, float>::type;
+    float px[4], py[4];
+    St C[4][3], T[4];
     bool valid[4];
     uint32_t nev[4], ncov[4];
     uint32_t alive = 0;
@@ -720,32 +767,32 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         valid[s] = X < W && Y < H;
         px[s] = (float)X + 0.5f;
         py[s] = (float)Y + 0.5f;
-        C[s][0] = C[s][1] = C[s][2] = 0.f;
-        T[s] = 1.f;
+        C[s][0] = C[s][1] = C[s][2] = (St)0.f;
+        T[s] = (St)1.f;
         nev[s] = ncov[s] = 0;
         if (ballot(valid[s])) alive |= 1u << s;
     }
     int nvis = *nvis_ptr;
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     uint32_t nq = 0;
-    // chunks [32 c_begin, cend) of this item (a 2048-position column is 32 chunks)
+    // chunks [COL_CHUNKS c_begin, cend) of this item
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
-    const int nch = (nvis + 63) / 64;
-    const int cend = c_end >= wpr ? nch : min(nch, c_end * 32);
-    int cursor = c_begin * 32;                    // wave 0's position in the walk
+    const int nch = (nvis + CHUNK_SPLATS - 1) / CHUNK_SPLATS;
+    const int cend = c_end >= ncol ? nch : min(nch, c_end * COL_CHUNKS);
+    int cursor = c_begin * COL_CHUNKS;            // wave 0's position in the walk
     // The backward's schedule: each wave counts the splats of its culled lists until every one of
     // its pixels has T below the backward's T-cull threshold, which is the work the backward's
     // wave will do on this tile (it walks the same lists and stops there).
-    uint32_t wl = 0;
+    uint32_t wl = 0, nwalk = 0, nempty = 0, nchk = 0, nbat = 0;
     bool wsat = false;
     for (;;) {
-        if (wave == 0) next_round(w, trow, cend, lane, cursor);
+        if (wave == 0) next_round<ROUND_CHUNKS>(w, trow, cend, lane, cursor);
         __syncthreads();
         if (w.nchunk == 0) break;
-        scan_round(w, rect, nvis, ttx, tty, wave, lane, lt);
+        scan_round<ROUND_CHUNKS>(w, rect, nvis, ttx, tty, wave, lane, lt);
         __syncthreads();
         const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
-        if (INSTR) nq += total;
+        if (INSTR) { nq += total; nchk += w.nchunk; nbat += (total + BATCH - 1) / BATCH; }
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
             stage(w, rec, b0, total, tid);
@@ -754,6 +801,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
             if (!TCULL || alive) {
                 const int nlist = cull_batch(w, m, wave, lane, lt, cx0, cy0);
                 if (!wsat) wl += (uint32_t)nlist;
+                if (INSTR) nwalk += (uint32_t)nlist;
                 for (int i = 0; i < nlist; ++i) {
                     const uint32_t ent = uniform((uint32_t)w.list[wave][i]);
                     const int k = (int)(ent & 0xFFu);
@@ -763,31 +811,45 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                     const float cb = __uint_as_float(Cw.x);
                     // the exponent's row part (log2 o folded in) for the lane's two pixel rows
                     float dxs[2], dys[2], er[2];
+                    const uint32_t sb = (ent >> 8) & (TCULL ? alive : 0xFu);
                     alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        if (((ent >> (8 + s)) & 1u) && (!TCULL || ((alive >> s) & 1u))) {
-                            const float al = clamp_alpha(alpha_raw(A, dxs[s & 1], dys[s >> 1], er[s >> 1]), amax);
-                            bool pass = al >= amin;
-                            if (TCULL) pass = pass && T[s] >= tmin;
+                        if ((sb >> s) & 1u) {
+                            // the test on the unclamped alpha: alpha_max > alpha_min, so
+                            // min(alpha_max, raw) >= alpha_min exactly when raw >= alpha_min
+                            const float raw = alpha_raw(A, dxs[s & 1], dys[s >> 1], er[s >> 1]);
+                            bool pass = raw >= amin;
+                            if (TCULL) pass = pass && (float)T[s] >= tmin;
                             if (pass) {
-                                const float wt = al * T[s];
-                                C[s][0] = fmaf(wt, B.z, C[s][0]);
-                                C[s][1] = fmaf(wt, B.w, C[s][1]);
-                                C[s][2] = fmaf(wt, cb, C[s][2]);
-                                T[s] = T[s] - wt;                // T (1 - alpha), Eq. 5
-                                if constexpr (RFMT >= 0) {
-                                    C[s][0] = fb_round<RFMT>(C[s][0]);
-                                    C[s][1] = fb_round<RFMT>(C[s][1]);
-                                    C[s][2] = fb_round<RFMT>(C[s][2]);
-                                    T[s] = fb_round<RFMT>(T[s]);
+                                const float al = clamp_alpha(raw, amax);
+                                const float Ts = (float)T[s];
+                                const float wt = al * Ts;
+                                if constexpr (RFMT == FB_F16) {   // one rounding to half each
+                                    C[s][0] = (St)fmaf(wt, B.z, (float)C[s][0]);
+                                    C[s][1] = (St)fmaf(wt, B.w, (float)C[s][1]);
+                                    C[s][2] = (St)fmaf(wt, cb, (float)C[s][2]);
+                                    T[s] = (St)fmaf(-Ts, al, Ts);   // T (1 - alpha), Eq. 5
+                                } else {
+                                    C[s][0] = fmaf(wt, B.z, C[s][0]);
+                                    C[s][1] = fmaf(wt, B.w, C[s][1]);
+                                    C[s][2] = fmaf(wt, cb, C[s][2]);
+                                    T[s] = Ts - wt;                 // T (1 - alpha), Eq. 5
+                                    if constexpr (RFMT >= 0) {
+                                        C[s][0] = fb_round<RFMT>(C[s][0]);
+                                        C[s][1] = fb_round<RFMT>(C[s][1]);
+                                        C[s][2] = fb_round<RFMT>(C[s][2]);
+                                        T[s] = fb_round<RFMT>(T[s]);
+                                    }
                                 }
                             }
                             if (INSTR) {
                                 nev[s] += valid[s];
                                 ncov[s] += (pass && valid[s]);
+                                nempty += ballot(pass && valid[s]) == 0ull;
                             }
-                            if (TCULL && !ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
+                            if (TCULL && !ballot(valid[s] && (float)T[s] >= tmin))
+                                alive &= ~(1u << s);
                         }
                     }
                 }
@@ -795,7 +857,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
             if (!wsat) {
                 bool a = false;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) a = a || (valid[s] && T[s] >= tsat);
+                for (int s = 0; s < 4; ++s) a = a || (valid[s] && (float)T[s] >= tsat);
                 wsat = ballot(a) == 0ull;
             }
             if (TCULL && lane == 0) w.alive[wave] = (int)alive;
@@ -829,7 +891,8 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int lxp = (wave & 1) * 16 + (s & 1) * 8 + lx, lyp = (wave >> 1) * 16 + (s >> 1) * 8 + ly;
-            part[lyp * TILE + lxp] = make_float4(C[s][0], C[s][1], C[s][2], T[s]);
+            part[lyp * TILE + lxp] = make_float4((float)C[s][0], (float)C[s][1], (float)C[s][2],
+                                                 (float)T[s]);
         }
         return;
     }
@@ -842,8 +905,9 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         const size_t i = vp + (size_t)Y * W + X;
         const size_t ic = 2 * vp + i;             // channel 0 of out_rgb's [3][H][W] view
         // the background behind the last splat (a final blend in per-fragment mode)
-        float4 v = make_float4(fmaf(T[s], bg0, C[s][0]), fmaf(T[s], bg1, C[s][1]),
-                               fmaf(T[s], bg2, C[s][2]), T[s]);
+        const float Ts = (float)T[s];
+        float4 v = make_float4(fmaf(Ts, bg0, (float)C[s][0]), fmaf(Ts, bg1, (float)C[s][1]),
+                               fmaf(Ts, bg2, (float)C[s][2]), Ts);
         if constexpr (RFMT >= 0) {
             v.x = fb_round<RFMT>(v.x); v.y = fb_round<RFMT>(v.y); v.z = fb_round<RFMT>(v.z);
         }
@@ -865,6 +929,12 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
             if (wave == 0) atomicAdd(&stats[0], (unsigned long long)nq);
             atomicAdd(&stats[1], (unsigned long long)e);
             atomicAdd(&stats[2], (unsigned long long)c);
+            atomicAdd(&stats[10], (unsigned long long)nwalk);
+            atomicAdd(&stats[11], (unsigned long long)nempty);
+            if (wave == 0) {
+                atomicAdd(&stats[12], (unsigned long long)nchk);
+                atomicAdd(&stats[13], (unsigned long long)nbat);
+            }
         }
     }
 }
@@ -1064,13 +1134,13 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     const bool lane_acc = TILEM || (mode == GS_REDUCE_HYBRID_LANE || mode == GS_REDUCE_TILE);
 
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
-    const int nch = (nvis + 63) / 64;
+    const int nch = (nvis + CHUNK_SPLATS - 1) / CHUNK_SPLATS;
     int cursor = 0;                               // wave 0's position in the walk
     for (;;) {
-        if (wave == 0) next_round(w, trow, nch, lane, cursor);
+        if (wave == 0) next_round<BWD_ROUND_CHUNKS>(w, trow, nch, lane, cursor);
         __syncthreads();
         if (w.nchunk == 0) break;
-        scan_round(w, rect, nvis, ttx, tty, wave, lane, lt);
+        scan_round<BWD_ROUND_CHUNKS>(w, rect, nvis, ttx, tty, wave, lane, lt);
         __syncthreads();
         const int total = w.segn[0] + w.segn[1] + w.segn[2] + w.segn[3];
         if (INSTR) nq += total;
@@ -1106,8 +1176,9 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                     // the forward's alpha (alpha_raw), with a' u kept for the gradient
                     const float araw = __builtin_amdgcn_exp2f(fmaf(au, u, er[s >> 1]));
                     const float al = clamp_alpha(araw, amax);
-                    // cullingFlag: splat boundary (alpha < 1/255), then T-Culling (T < 1e-4)
-                    const bool live = valid[s] && al >= amin && T[s] >= tmin;
+                    // cullingFlag: splat boundary (alpha < 1/255, tested on the unclamped alpha
+                    // as in the forward), then T-Culling (T < 1e-4)
+                    const bool live = valid[s] && araw >= amin && T[s] >= tmin;
                     // the fragment's nine gradients: added straight into the lane's sums in the
                     // tile reduction, else kept for the per-fragment reduction
                     float g[9];
@@ -1324,10 +1395,11 @@ static int tiles_of(int width, int height) {
     return ((width + TILE - 1) / TILE) * ((height + TILE - 1) / TILE);
 }
 
-// Words per tile row of the occupancy bitmap (0: no bitmap, every chunk is tested).
+// Words per tile row of the occupancy bitmap (0: no bitmap, every chunk is tested): COL_WORDS
+// per column of SETUP_SPAN sorted positions, one column per setup block.
 static int bitmap_wpr(int n, int width, int height) {
     const size_t nt = (size_t)tiles_of(width, height);
-    const size_t wpr = ((size_t)n + SETUP_SPAN - 1) / SETUP_SPAN;   // one word per setup block
+    const size_t wpr = ((size_t)n + SETUP_SPAN - 1) / SETUP_SPAN * COL_WORDS;
     return (n > 0 && nt <= (size_t)MAX_LDS_TILES && nt * wpr * 4 <= BITMAP_BUDGET) ? (int)wpr : 0;
 }
 
@@ -1341,7 +1413,7 @@ size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
     size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up((size_t)n * 4) +
                align_up(16 * 8) + align_up(nt * 4) * 4 + align_up(nt * wpr * 4);
     if (split_ok(n, width, height))
-        b += align_up(nt * wpr * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
+        b += align_up(nt * (wpr / COL_WORDS) * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
              2 * align_up(ITEMS_PER_TILE * nt * 4) + 2 * align_up(nt * 4) +
              align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
     // the setup's per-id staging and the backward's gradient slots share one region (64 B per
@@ -1370,7 +1442,7 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     r.colcnt = nullptr; r.items = nullptr; r.item_w = nullptr; r.item_order = nullptr;
     r.tile_first = nullptr; r.tile_k = nullptr; r.partial = nullptr;
     if (r.split) {
-        r.colcnt = (uint16_t*)p;    p += align_up(nt * (size_t)r.wpr * 2);
+        r.colcnt = (uint16_t*)p;    p += align_up(nt * (size_t)(r.wpr / COL_WORDS) * 2);
         r.items = (int4*)p;         p += align_up(ITEMS_PER_TILE * nt * 16);
         r.item_w = (uint32_t*)p;    p += align_up(ITEMS_PER_TILE * nt * 4);
         r.item_order = (int32_t*)p; p += align_up(ITEMS_PER_TILE * nt * 4);
@@ -1405,7 +1477,8 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
         hipLaunchKernelGGL(k_raster_pack, dim3((n + 255) / 256, V), dim3(256), 0, s, n, means2d,
                            conics, opac, rgb, width, height, cfg.alpha_min, sat, (IdRec*)r.idrec,
                            vs.ws);
-        const size_t lds = ntiles <= MAX_LDS_TILES ? (size_t)ntiles * 8 : 0;
+        const size_t lds =
+            ntiles <= MAX_LDS_TILES ? ((size_t)ntiles * COL_WORDS + (ntiles + 1) / 2) * 4 : 0;
         hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V),
                            dim3(SETUP_NT), lds, s, n, sorted_ids, n_visible, (const IdRec*)r.idrec, tiles_x, ntiles,
                            (Rec*)r.rec, (uint2*)r.rect, r.inv, r.weights, r.bits, r.wpr, r.colcnt,
@@ -1415,7 +1488,8 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
                        r.split, r.tile_k, r.tile_first, r.counters, r.bwd_w, vs.ws);
     if (r.split) {
         hipLaunchKernelGGL(k_plan_cuts, dim3(ntiles, V), dim3(64), 0, s, r.weights,
-                           (const uint16_t*)r.colcnt, r.wpr, ntiles, (const int32_t*)r.tile_k,
+                           (const uint16_t*)r.colcnt, r.wpr / COL_WORDS, ntiles,
+                           (const int32_t*)r.tile_k,
                            (const int32_t*)r.tile_first, r.items, r.item_w, vs.ws);
         hipLaunchKernelGGL(k_plan_items, dim3(1, V), dim3(NBUCKETS), 0, s,
                            (const uint32_t*)r.item_w, ntiles, (const unsigned long long*)r.counters,
