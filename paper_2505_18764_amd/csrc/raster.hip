@@ -802,54 +802,60 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                 const int nlist = cull_batch(w, m, wave, lane, lt, cx0, cy0);
                 if (!wsat) wl += (uint32_t)nlist;
                 if (INSTR) nwalk += (uint32_t)nlist;
-                for (int i = 0; i < nlist; ++i) {
-                    const uint32_t ent = uniform((uint32_t)w.list[wave][i]);
-                    const int k = (int)(ent & 0xFFu);
-                    const float4 A = w.rec[k].a;
-                    const float4 B = w.rec[k].b;
-                    const uint4 Cw = w.rec[k].c;
-                    const float cb = __uint_as_float(Cw.x);
-                    // the exponent's row part (log2 o folded in) for the lane's two pixel rows
-                    float dxs[2], dys[2], er[2];
-                    const uint32_t sb = (ent >> 8) & (TCULL ? alive : 0xFu);
-                    alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
+                // the list is read 64 entries at a time, one per lane, and each entry is taken
+                // from its lane by readlane (no LDS round trip per entry)
+                for (int i0 = 0; i0 < nlist; i0 += 64) {
+                    const int ents = i0 + lane < nlist ? (int)w.list[wave][i0 + lane] : 0;
+                    const int iend = min(64, nlist - i0);
+                    for (int i = 0; i < iend; ++i) {
+                        const uint32_t ent = (uint32_t)__builtin_amdgcn_readlane(ents, i);
+                        const int k = (int)(ent & 0xFFu);
+                        const float4 A = w.rec[k].a;
+                        const float4 B = w.rec[k].b;
+                        const uint4 Cw = w.rec[k].c;
+                        const float cb = __uint_as_float(Cw.x);
+                        // the exponent's row part (log2 o folded in) for the lane's two pixel rows
+                        float dxs[2], dys[2], er[2];
+                        const uint32_t sb = (ent >> 8) & (TCULL ? alive : 0xFu);
+                        alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        if ((sb >> s) & 1u) {
-                            // the test on the unclamped alpha: alpha_max > alpha_min, so
-                            // min(alpha_max, raw) >= alpha_min exactly when raw >= alpha_min
-                            const float raw = alpha_raw(A, dxs[s & 1], dys[s >> 1], er[s >> 1]);
-                            bool pass = raw >= amin;
-                            if (TCULL) pass = pass && (float)T[s] >= tmin;
-                            if (pass) {
-                                const float al = clamp_alpha(raw, amax);
-                                const float Ts = (float)T[s];
-                                const float wt = al * Ts;
-                                if constexpr (RFMT == FB_F16) {   // one rounding to half each
-                                    C[s][0] = (St)fmaf(wt, B.z, (float)C[s][0]);
-                                    C[s][1] = (St)fmaf(wt, B.w, (float)C[s][1]);
-                                    C[s][2] = (St)fmaf(wt, cb, (float)C[s][2]);
-                                    T[s] = (St)fmaf(-Ts, al, Ts);   // T (1 - alpha), Eq. 5
-                                } else {
-                                    C[s][0] = fmaf(wt, B.z, C[s][0]);
-                                    C[s][1] = fmaf(wt, B.w, C[s][1]);
-                                    C[s][2] = fmaf(wt, cb, C[s][2]);
-                                    T[s] = Ts - wt;                 // T (1 - alpha), Eq. 5
-                                    if constexpr (RFMT >= 0) {
-                                        C[s][0] = fb_round<RFMT>(C[s][0]);
-                                        C[s][1] = fb_round<RFMT>(C[s][1]);
-                                        C[s][2] = fb_round<RFMT>(C[s][2]);
-                                        T[s] = fb_round<RFMT>(T[s]);
+                        for (int s = 0; s < 4; ++s) {
+                            if ((sb >> s) & 1u) {
+                                // the test on the unclamped alpha: alpha_max > alpha_min, so
+                                // min(alpha_max, raw) >= alpha_min exactly when raw >= alpha_min
+                                const float raw = alpha_raw(A, dxs[s & 1], dys[s >> 1], er[s >> 1]);
+                                bool pass = raw >= amin;
+                                if (TCULL) pass = pass && (float)T[s] >= tmin;
+                                if (pass) {
+                                    const float al = clamp_alpha(raw, amax);
+                                    const float Ts = (float)T[s];
+                                    const float wt = al * Ts;
+                                    if constexpr (RFMT == FB_F16) {   // one rounding to half each
+                                        C[s][0] = (St)fmaf(wt, B.z, (float)C[s][0]);
+                                        C[s][1] = (St)fmaf(wt, B.w, (float)C[s][1]);
+                                        C[s][2] = (St)fmaf(wt, cb, (float)C[s][2]);
+                                        T[s] = (St)fmaf(-Ts, al, Ts);   // T (1 - alpha), Eq. 5
+                                    } else {
+                                        C[s][0] = fmaf(wt, B.z, C[s][0]);
+                                        C[s][1] = fmaf(wt, B.w, C[s][1]);
+                                        C[s][2] = fmaf(wt, cb, C[s][2]);
+                                        T[s] = Ts - wt;                 // T (1 - alpha), Eq. 5
+                                        if constexpr (RFMT >= 0) {
+                                            C[s][0] = fb_round<RFMT>(C[s][0]);
+                                            C[s][1] = fb_round<RFMT>(C[s][1]);
+                                            C[s][2] = fb_round<RFMT>(C[s][2]);
+                                            T[s] = fb_round<RFMT>(T[s]);
+                                        }
                                     }
                                 }
+                                if (INSTR) {
+                                    nev[s] += valid[s];
+                                    ncov[s] += (pass && valid[s]);
+                                    nempty += ballot(pass && valid[s]) == 0ull;
+                                }
+                                if (TCULL && !ballot(valid[s] && (float)T[s] >= tmin))
+                                    alive &= ~(1u << s);
                             }
-                            if (INSTR) {
-                                nev[s] += valid[s];
-                                ncov[s] += (pass && valid[s]);
-                                nempty += ballot(pass && valid[s]) == 0ull;
-                            }
-                            if (TCULL && !ballot(valid[s] && (float)T[s] >= tmin))
-                                alive &= ~(1u << s);
                         }
                     }
                 }
@@ -1152,131 +1158,139 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
             const int m = min(BATCH, total - b0);
             pend = m;
             const int nlist = alive ? cull_batch(w, m, wave, lane, lt, cx0, cy0) : 0;
-            for (int i = 0; i < nlist && alive; ++i) {
-                const uint32_t ent = uniform((uint32_t)w.list[wave][i]);
-                const int k = (int)(ent & 0xFFu);
-                const float4 A = w.rec[k].a;
-                const float4 B = w.rec[k].b;
-                const uint4 Cw = w.rec[k].c;
-                const float cr = B.z, cg = B.w, cb = __uint_as_float(Cw.x);
-                float* gp = grad + (size_t)uniform(Cw.w) * GRAD_STRIDE;
-                float dxs[2], dys[2], er[2];
-                alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
-                const float inv_o = __builtin_amdgcn_rcpf(B.y);
-                float acc[9];
+            // the list is read 64 entries at a time, one per lane (readlane takes each entry)
+            for (int i0 = 0; i0 < nlist && alive; i0 += 64) {
+                const int ents = i0 + lane < nlist ? (int)w.list[wave][i0 + lane] : 0;
+                const int iend = min(64, nlist - i0);
+                for (int i = 0; i < iend && alive; ++i) {
+                    const uint32_t ent = (uint32_t)__builtin_amdgcn_readlane(ents, i);
+                    const int k = (int)(ent & 0xFFu);
+                    const float4 A = w.rec[k].a;
+                    const float4 B = w.rec[k].b;
+                    const uint4 Cw = w.rec[k].c;
+                    const float cr = B.z, cg = B.w, cb = __uint_as_float(Cw.x);
+                    float* gp = grad + (size_t)uniform(Cw.w) * GRAD_STRIDE;
+                    float dxs[2], dys[2], er[2];
+                    alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
+                    const float inv_o = __builtin_amdgcn_rcpf(B.y);
+                    float acc[9];
 #pragma unroll
-                for (int j = 0; j < 9; ++j) acc[j] = 0.f;
-                bool acc_live = false;
+                    for (int j = 0; j < 9; ++j) acc[j] = 0.f;
+                    bool acc_live = false;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    if (!((ent >> (8 + s)) & 1u) || !((alive >> s) & 1u)) continue;
-                    const float dx = dxs[s & 1], dy = dys[s >> 1];
-                    const float u = fmaf(A.w, dy, dx);
-                    const float au = A.z * u;
-                    // the forward's alpha (alpha_raw), with a' u kept for the gradient
-                    const float araw = __builtin_amdgcn_exp2f(fmaf(au, u, er[s >> 1]));
-                    const float al = clamp_alpha(araw, amax);
-                    // cullingFlag: splat boundary (alpha < 1/255, tested on the unclamped alpha
-                    // as in the forward), then T-Culling (T < 1e-4)
-                    const bool live = valid[s] && araw >= amin && T[s] >= tmin;
-                    // the fragment's nine gradients: added straight into the lane's sums in the
-                    // tile reduction, else kept for the per-fragment reduction
-                    float g[9];
-                    if constexpr (!TILEM) {
+                    for (int s = 0; s < 4; ++s) {
+                        if (!((ent >> (8 + s)) & 1u) || !((alive >> s) & 1u)) continue;
+                        const float dx = dxs[s & 1], dy = dys[s >> 1];
+                        const float u = fmaf(A.w, dy, dx);
+                        const float au = A.z * u;
+                        // the forward's alpha (alpha_raw), with a' u kept for the gradient
+                        const float araw = __builtin_amdgcn_exp2f(fmaf(au, u, er[s >> 1]));
+                        const float al = clamp_alpha(araw, amax);
+                        // cullingFlag: splat boundary (alpha < 1/255, tested on the unclamped alpha
+                        // as in the forward), then T-Culling (T < 1e-4)
+                        const bool live = valid[s] && araw >= amin && T[s] >= tmin;
+                        // the fragment's nine gradients: added straight into the lane's sums in the
+                        // tile reduction, else kept for the per-fragment reduction
+                        float g[9];
+                        if constexpr (!TILEM) {
 #pragma unroll
-                        for (int j = 0; j < 9; ++j) g[j] = 0.f;
-                    }
-                    if (live) {
-                        const float Ti = T[s];
-                        const float wt = al * Ti;
-                        // Eq. 3: dL/dc = dL/dC alpha T
-                        if constexpr (TILEM) {
-                            acc[6] = fmaf(G[s][0], wt, acc[6]);
-                            acc[7] = fmaf(G[s][1], wt, acc[7]);
-                            acc[8] = fmaf(G[s][2], wt, acc[8]);
-                            acc_live = true;
-                        } else {
-                            g[6] = G[s][0] * wt;
-                            g[7] = G[s][1] * wt;
-                            g[8] = G[s][2] * wt;
+                            for (int j = 0; j < 9; ++j) g[j] = 0.f;
                         }
-                        // Eq. 7: dL/dalpha = dL/dC . (c T - C') / (1 - alpha), and the final
-                        // transmittance's share
-                        const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) + G[s][1] * (cg * Ti - Cp[s][1]) +
-                                          G[s][2] * (cb * Ti - Cp[s][2]) - gTT[s]) *
-                                         __builtin_amdgcn_rcpf(1.f - al);
-                        // Eqs. 5, 6: the state update, stored back
-                        Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
-                        Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
-                        Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
-                        T[s] = Ti - wt;                                   // Eq. 5
-                        if constexpr (RFMT >= 0) {
-                            Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
-                            Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
-                            Cp[s][2] = fb_round<RFMT>(Cp[s][2]);
-                            T[s] = fb_round<RFMT>(T[s]);
-                        }
-                        // bwd_diff: alpha = o exp(-q/2) (zero gradient where clamped);
-                        // dq/dmu = -2 Q d, in the factored form: Q d = (a u, k a u + (det/a) dy),
-                        // so dp/dd = (2 a' u, k 2 a' u + 2 d' dy) with the pre-scaled factors
-                        if (araw < amax) {
-                            const float gq = -0.5f * ga * araw;          // dL/dq
-                            const float gm = -2.f * ga * araw * (1.0f / LOG2E);
-                            const float gy = fmaf(A.w, au, B.x * dy);
+                        if (live) {
+                            const float Ti = T[s];
+                            const float wt = al * Ti;
+                            // Eq. 3: dL/dc = dL/dC alpha T
                             if constexpr (TILEM) {
-                                acc[5] = fmaf(ga * araw, inv_o, acc[5]);   // dalpha/do = exp(-q/2)
-                                acc[0] = fmaf(gm, au, acc[0]);
-                                acc[1] = fmaf(gm, gy, acc[1]);
-                                const float gdx = gq * dx;
-                                acc[2] = fmaf(gdx, dx, acc[2]);
-                                acc[3] = fmaf(2.f * gdx, dy, acc[3]);
-                                acc[4] = fmaf(gq * dy, dy, acc[4]);
+                                acc[6] = fmaf(G[s][0], wt, acc[6]);
+                                acc[7] = fmaf(G[s][1], wt, acc[7]);
+                                acc[8] = fmaf(G[s][2], wt, acc[8]);
+                                acc_live = true;
                             } else {
-                                g[5] = ga * araw * inv_o;           // dalpha/do = exp(-q/2)
-                                g[0] = gm * au;
-                                g[1] = gm * gy;
-                                g[2] = gq * dx * dx;
-                                g[3] = 2.f * gq * dx * dy;
-                                g[4] = gq * dy * dy;
+                                g[6] = G[s][0] * wt;
+                                g[7] = G[s][1] * wt;
+                                g[8] = G[s][2] * wt;
+                            }
+                            // Eq. 7: dL/dalpha = dL/dC . (c T - C') / (1 - alpha), and the final
+                            // transmittance's share
+                            const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) +
+                                              G[s][1] * (cg * Ti - Cp[s][1]) +
+                                              G[s][2] * (cb * Ti - Cp[s][2]) - gTT[s]) *
+                                             __builtin_amdgcn_rcpf(1.f - al);
+                            // Eqs. 5, 6: the state update, stored back
+                            Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
+                            Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
+                            Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
+                            T[s] = Ti - wt;                                   // Eq. 5
+                            if constexpr (RFMT >= 0) {
+                                Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
+                                Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
+                                Cp[s][2] = fb_round<RFMT>(Cp[s][2]);
+                                T[s] = fb_round<RFMT>(T[s]);
+                            }
+                            // bwd_diff: alpha = o exp(-q/2) (zero gradient where clamped);
+                            // dq/dmu = -2 Q d, in the factored form:
+                            // Q d = (a u, k a u + (det/a) dy), so
+                            // dp/dd = (2 a' u, k 2 a' u + 2 d' dy) with the pre-scaled factors
+                            if (araw < amax) {
+                                const float gq = -0.5f * ga * araw;          // dL/dq
+                                const float gm = -2.f * ga * araw * (1.0f / LOG2E);
+                                const float gy = fmaf(A.w, au, B.x * dy);
+                                if constexpr (TILEM) {
+                                    // dalpha/do = exp(-q/2)
+                                    acc[5] = fmaf(ga * araw, inv_o, acc[5]);
+                                    acc[0] = fmaf(gm, au, acc[0]);
+                                    acc[1] = fmaf(gm, gy, acc[1]);
+                                    const float gdx = gq * dx;
+                                    acc[2] = fmaf(gdx, dx, acc[2]);
+                                    acc[3] = fmaf(2.f * gdx, dy, acc[3]);
+                                    acc[4] = fmaf(gq * dy, dy, acc[4]);
+                                } else {
+                                    g[5] = ga * araw * inv_o;           // dalpha/do = exp(-q/2)
+                                    g[0] = gm * au;
+                                    g[1] = gm * gy;
+                                    g[2] = gq * dx * dx;
+                                    g[3] = 2.f * gq * dx * dy;
+                                    g[4] = gq * dy * dy;
+                                }
                             }
                         }
-                    }
-                    if (INSTR) {
-                        cnt.evaluated += valid[s];
-                        cnt.live += live;
-                        nlive[s] += live;
-                    }
-                    if constexpr (!TILEM) {
-                        if (lane_acc) {
+                        if (INSTR) {
+                            cnt.evaluated += valid[s];
+                            cnt.live += live;
+                            nlive[s] += live;
+                        }
+                        if constexpr (!TILEM) {
+                            if (lane_acc) {
 #pragma unroll
-                            for (int j = 0; j < 9; ++j) acc[j] += g[j];
-                            acc_live = acc_live || live;
-                        } else {
-                            reduce_commit<INSTR>(g, live, gp, mode, X, lane, cnt);
+                                for (int j = 0; j < 9; ++j) acc[j] += g[j];
+                                acc_live = acc_live || live;
+                            } else {
+                                reduce_commit<INSTR>(g, live, gp, mode, X, lane, cnt);
+                            }
                         }
+                        // sub-blocks whose pixels are all T-culled drop out; checked every fourth
+                        // list entry (a later check only costs a few fragments that the T test
+                        // already rejects)
+                        if ((i & 3) == 3 || i + 1 == nlist)
+                            if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
                     }
-                    // sub-blocks whose pixels are all T-culled drop out; checked every fourth
-                    // list entry (a later check only costs a few fragments that the T test
-                    // already rejects)
-                    if ((i & 3) == 3 || i + 1 == nlist)
-                        if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
-                }
-                if (tile_acc) {
-                    // the wave's lane sums reduced at once; the first lane of each 16-lane row
-                    // adds its two (row 0: three) totals to the tile's LDS accumulator
-                    if (ballot(acc_live)) {
-                        float ra, rb, rc;
-                        wave_sum9(acc, ra, rb, rc);
-                        if ((lane & 15) == 0) {
-                            const int row = lane >> 4, j0 = ((row & 1) << 1) | (row >> 1);
-                            atomicAdd(tg + k * 9 + j0, ra);
-                            atomicAdd(tg + k * 9 + j0 + 4, rb);
-                            if (row == 0) atomicAdd(tg + k * 9 + 8, rc);
+                    if (tile_acc) {
+                        // the wave's lane sums reduced at once; the first lane of each 16-lane row
+                        // adds its two (row 0: three) totals to the tile's LDS accumulator
+                        if (ballot(acc_live)) {
+                            float ra, rb, rc;
+                            wave_sum9(acc, ra, rb, rc);
+                            if ((lane & 15) == 0) {
+                                const int row = lane >> 4, j0 = ((row & 1) << 1) | (row >> 1);
+                                atomicAdd(tg + k * 9 + j0, ra);
+                                atomicAdd(tg + k * 9 + j0 + 4, rb);
+                                if (row == 0) atomicAdd(tg + k * 9 + 8, rc);
+                            }
+                            if (INSTR && lane == 0) { cnt.wave_red += 1; cnt.cohesive += 1; }
                         }
-                        if (INSTR && lane == 0) { cnt.wave_red += 1; cnt.cohesive += 1; }
+                    } else if (lane_acc) {
+                        reduce_commit<INSTR>(acc, acc_live, gp, GS_REDUCE_HYBRID, X, lane, cnt);
                     }
-                } else if (lane_acc) {
-                    reduce_commit<INSTR>(acc, acc_live, gp, GS_REDUCE_HYBRID, X, lane, cnt);
                 }
             }
             if (lane == 0) w.alive[wave] = (int)alive;

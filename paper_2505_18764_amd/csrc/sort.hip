@@ -13,7 +13,7 @@
 namespace gsr {
 
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ROUNDS = 16;
+constexpr int SORT_ROUNDS = 8;
 constexpr int SORT_ITEMS = SORT_THREADS * SORT_ROUNDS;   // keys per block
 constexpr int SCAN_ITEMS = 4096;                         // entries per scan block (256 x 16)
 
