@@ -96,6 +96,26 @@ def test_ragged_sizes(W, H, n, seed):
     _check(out, ref)
 
 
+def test_large_image_without_bitmap():
+    """An image of more than 8192 tiles (3000 x 3000 px = 8836 tiles) is set up without the tile
+    occupancy bitmap: every chunk of the sorted splats is tested against every tile and the tile
+    weights are sampled. The splats lie in the top-left 160 x 120 px; there the image, coverage and
+    live counts must equal the oracle's on a 160 x 120 image of the same splats, and with dL/dC
+    zero outside that corner so must the gradients. Far from the corner every pixel is background."""
+    W, H, w, h = 3000, 3000, 160, 120
+    s = synth.splats2d(n=800, width=w, height=h, seed=31)
+    g = synth.image_grad(w, h, 32)
+    G = np.zeros((3, H, W), np.float32)
+    G[:, :h, :w] = g
+    out = _run(s, W, H, G, R.RasterConfig())
+    ref = _oracle(s, w, h, g, oracle.OracleConfig(**BAND))
+    crop = dict(out, img=out["img"][:, :h, :w], T=out["T"][:h, :w], cov=out["cov"][:h, :w],
+                live=out["live"][:h, :w])
+    _check(crop, ref)
+    assert (out["img"][:, :, 4 * w:] == 0).all() and (out["T"][:, 4 * w:] == 1).all()
+    assert (out["img"][:, 4 * h:, :] == 0).all() and (out["T"][4 * h:, :] == 1).all()
+
+
 def test_n_zero_and_offscreen():
     W, H = 40, 30
     for s in (synth.splats2d(n=0, width=W, height=H, seed=1),):
