@@ -57,7 +57,6 @@ constexpr int CHUNK_SPLATS = 16;        // sorted splats per bit of the tile occ
 // a smaller round stages fewer splats past that point.
 constexpr int ROUND_CHUNKS = 192;
 constexpr int BWD_ROUND_CHUNKS = 64;
-constexpr int SPAN = ROUND_CHUNKS / 4 * CHUNK_SPLATS;   // hits one wave can hold per round
 constexpr size_t BITMAP_BUDGET = 1024u << 20;  // the bitmap is skipped above this many bytes
 
 // ---- schedule ------------------------------------------------------------------------------
@@ -514,12 +513,15 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
 // order; the hits are staged into LDS in batches. A dense tile's round is 16 RC splats; a
 // sparse tile skips the chunks none of whose splats touch it. Most (tile, splat) pairs are
 // sparse: a tile's splats lie far apart in depth order, so an occupied chunk holds one or two
-// hits, and the chunk size sets how many rectangles the walk tests per hit.
+// hits, and the chunk size sets how many rectangles the walk tests per hit. The LDS state is sized
+// for the round length RC.
+template <int RC>
 struct Walk {
+    static constexpr int SPAN = RC / 4 * CHUNK_SPLATS;   // hits one wave can hold per round
     Rec rec[BATCH];             // first: its reads take small immediate offsets
     uint16_t seg[4][SPAN];      // per wave: hits as chunk slot * CHUNK_SPLATS + splat
     uint16_t list[4][BATCH];
-    int chunk[ROUND_CHUNKS];    // the round's chunks, increasing
+    int chunk[RC];              // the round's chunks, increasing
     int nchunk;
     int segn[4];
     int alive[4];
@@ -557,7 +559,8 @@ __device__ __forceinline__ float clamp_alpha(float raw, float amax) {
 // A sub-block whose bound stays below p_min (with a margin far above the FP32 error of the
 // bound) holds no fragment with alpha >= alpha_min. The splats that reach at least one
 // sub-block are compacted in order into w.list[wave] as k | mask << 8; returns their count.
-__device__ __forceinline__ int cull_batch(Walk& w, int m, int wave, int lane, uint64_t lt,
+template <int RC>
+__device__ __forceinline__ int cull_batch(Walk<RC>& w, int m, int wave, int lane, uint64_t lt,
                                           float cx0, float cy0) {
     int cnt = 0;
     for (int k0 = 0; k0 < m; k0 += 64) {
@@ -594,9 +597,8 @@ __device__ __forceinline__ int cull_batch(Walk& w, int m, int wave, int lane, ui
 // cursor moved past them (every chunk counts as occupied without a bitmap). One bitmap word per
 // lane; a wave prefix sum of the words' popcounts places each lane's chunks.
 template <int RC>
-__device__ __forceinline__ void next_round(Walk& w, const uint32_t* __restrict__ trow, int cend,
-                                           int lane, int& cursor) {
-    static_assert(RC <= ROUND_CHUNKS, "w.chunk holds ROUND_CHUNKS");
+__device__ __forceinline__ void next_round(Walk<RC>& w, const uint32_t* __restrict__ trow,
+                                           int cend, int lane, int& cursor) {
     int cc = cursor, got = 0;
     if (!trow) {
         got = min(RC, max(0, cend - cc));
@@ -644,11 +646,10 @@ __device__ __forceinline__ void next_round(Walk& w, const uint32_t* __restrict__
 // writes the in-order hits to w.seg[wave] (slot * CHUNK_SPLATS + splat) and their count to
 // w.segn.
 template <int RC>
-__device__ __forceinline__ void scan_round(Walk& w, const uint2* __restrict__ rect, int nvis,
+__device__ __forceinline__ void scan_round(Walk<RC>& w, const uint2* __restrict__ rect, int nvis,
                                            uint32_t ttx, uint32_t tty, int wave, int lane,
                                            uint64_t lt) {
     constexpr int PER_STEP = 64 / CHUNK_SPLATS, WAVE_CHUNKS = RC / 4;
-    static_assert(WAVE_CHUNKS * CHUNK_SPLATS <= SPAN, "w.seg holds SPAN hits per wave");
     int cnt = 0;
     const int s0 = wave * WAVE_CHUNKS, s1 = min(w.nchunk, s0 + WAVE_CHUNKS);
     const int sub = lane / CHUNK_SPLATS, idx = lane % CHUNK_SPLATS;
@@ -671,7 +672,8 @@ __device__ __forceinline__ void scan_round(Walk& w, const uint2* __restrict__ re
 }
 
 // Stages hits [b0, b0 + BATCH) of the round (in order across the four waves' lists).
-__device__ __forceinline__ void stage(Walk& w, const Rec* __restrict__ rec, int b0, int total,
+template <int RC>
+__device__ __forceinline__ void stage(Walk<RC>& w, const Rec* __restrict__ rec, int b0, int total,
                                       int tid) {
     const int e = b0 + tid;
     if (e < total) {
@@ -720,7 +722,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T,
     int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats,
     uint32_t* __restrict__ bwd_w, uint64_t vws) {
-    __shared__ Walk w;
+    __shared__ Walk<ROUND_CHUNKS> w;
     if constexpr (MULTI) {   // this view's walk state (its outputs are located at the write-back)
         nvis_ptr = view_at(nvis_ptr, 1);
         bwd_w = view_bytes(bwd_w, vws);
@@ -1039,9 +1041,10 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
 // GS_REDUCE_TILE: thread t owns entry t of the staged batch's LDS accumulator; it adds the
 // entry to the splat's gradient slot (one set of global atomics per splat and tile) and clears it.
 // Called before entry t is restaged and once after the walk.
-template <bool INSTR>
-__device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Walk& w, int pend,
-                                                int tid, float* __restrict__ grad, BwdCounts& cnt) {
+template <bool INSTR, int RC>
+__device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Walk<RC>& w,
+                                                int pend, int tid, float* __restrict__ grad,
+                                                BwdCounts& cnt) {
     if (tid < pend) {
         float v[9];
         bool any = false;
@@ -1069,7 +1072,7 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     const float* __restrict__ dL_dimg, const float* __restrict__ dL_dT,
     int mode, int X, float* __restrict__ grad, float* __restrict__ bgpart,
     int32_t* __restrict__ out_live, unsigned long long* __restrict__ stats, uint64_t vws) {
-    __shared__ Walk w;
+    __shared__ Walk<BWD_ROUND_CHUNKS> w;
     __shared__ float tg[BATCH * 9];     // GS_REDUCE_TILE: per staged splat, the tile's gradient
     if constexpr (MULTI) {
         const uint64_t PV = (uint64_t)W * H;

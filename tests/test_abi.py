@@ -31,6 +31,40 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(L.exported_symbols())    # the binding covers the same names
 
 
+_CSIZE = {"float": 4, "int32_t": 4, "uint32_t": 4, "double": 8, "unsigned long long": 8}
+
+
+def _header_structs():
+    """{struct name: [(field, bytes)]} for the header's plain typedef structs."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"typedef struct (\w+) \{(.*?)\} \1;", src, flags=re.S):
+        fields = []
+        for stmt in m.group(2).split(";"):
+            stmt = " ".join(stmt.split())
+            if not stmt:
+                continue
+            tm = re.match(r"(unsigned long long|float|int32_t|uint32_t|double) (.*)", stmt)
+            assert tm, stmt
+            for part in tm.group(2).split(","):
+                am = re.fullmatch(r"(\w+)(?:\[(\d+)\])?", part.strip())
+                assert am, part
+                fields.append((am.group(1), _CSIZE[tm.group(1)] * int(am.group(2) or 1)))
+        out[m.group(1)] = fields
+    return out
+
+
+def test_ctypes_structs_match_the_header():
+    from paper_2505_18764_amd import _lib as L
+    hs = _header_structs()
+    for cname, py in (("gs_camera", L.GsCamera), ("gs_config", L.GsConfig),
+                      ("gs_stats", L.GsStats)):
+        got = [(name, ctypes.sizeof(t)) for name, t in py._fields_]
+        assert got == hs[cname], cname
+        assert ctypes.sizeof(py) == sum(b for _, b in hs[cname]), cname
+    assert ctypes.sizeof(L.GsStats) == 16 * 8
+
+
 def test_defaults_are_the_papers_constants():
     from paper_2505_18764_amd import _lib as L
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
