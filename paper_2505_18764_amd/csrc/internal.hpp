@@ -49,7 +49,6 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 struct RasterWs {
     void* rec;         // [n] records in sorted order
     void* rect;        // [n] uint2 tile rectangles
-    int32_t* inv;      // [n] sorted position of each splat id (written by the setup)
     void* idrec;       // [n] 64-byte per-id records, the setup's staging in id order
     float* grad;       // [n * GRAD_STRIDE] (backward only)
     float* bgpart;     // [tiles][4] per-tile dL/dbackground partial sums (backward only)

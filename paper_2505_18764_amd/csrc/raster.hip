@@ -28,8 +28,8 @@ constexpr int NT = 256;            // threads per workgroup
 constexpr int BATCH = 256;         // splat records staged in LDS at once
 
 // A staged splat: a = (mean x, mean y, a', k); b = (d', opacity, r, g);
-// c = (bits of colour b, sorted position, bits of p_min, 0) where p_min = log2(alpha_min / o) is
-// the least exponent whose alpha passes alpha_min.
+// c = (bits of colour b, bits of log2 o, bits of p_min, splat id) where p_min = log2(alpha_min / o)
+// is the least exponent whose alpha passes alpha_min.
 //
 // The conic Q = [[a, b], [b, c]] is stored in its LDL^T factors: q = d^T Q d =
 // a (dx + k dy)^2 + (det Q / a) dy^2 with k = b / a, a sum of two non-negative terms. The
@@ -41,7 +41,7 @@ constexpr int BATCH = 256;         // splat records staged in LDS at once
 // pre-scaled, a' = -log2(e) a / 2 and d' = -log2(e) det Q / (2a), so that the exponent of
 // alpha = o 2^p is p = a' u^2 + d' dy^2 = -q/2 log2(e), u = dx + k dy.
 // Fields: a = (mean x, mean y, a', k), b = (d', opacity, r, g), c = (b colour, log2 opacity,
-// p_min, sorted position); the forward reads c.x and c.y together.
+// p_min, splat id); the forward reads c.x and c.y together.
 struct __align__(16) Rec {
     float4 a;
     float4 b;
@@ -326,7 +326,7 @@ constexpr int MAX_LDS_TILES = 8192;
 constexpr uint32_t NO_TILE_X = 0xFFFFu;         // rect.x of a splat that touches no tile
 
 struct IdRec {
-    Rec r;          // c.w (the sorted position) is filled in by k_raster_setup
+    Rec r;          // c.w (the splat id) is filled in by k_raster_setup
     uint2 rect;     // tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16)
     uint2 pad;
 };
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(256) void k_raster_pack(
 __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
     int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
     const IdRec* __restrict__ idrec, int tiles_x, int ntiles, Rec* __restrict__ rec,
-    uint2* __restrict__ rect, int32_t* __restrict__ inv, uint32_t* __restrict__ weights,
+    uint2* __restrict__ rect, uint32_t* __restrict__ weights,
     uint32_t* __restrict__ bits, int wpr, uint16_t* __restrict__ colcnt, uint64_t vws) {
     // when ntiles <= MAX_LDS_TILES: [ntiles][COL_WORDS] chunk bits, then the tiles' 16-bit
     // counts two to a word (a count is at most SETUP_SPAN, so an add never carries across)
@@ -399,7 +399,6 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
     idrec = view_bytes(idrec, vws);
     rec = view_bytes(rec, vws);
     rect = view_bytes(rect, vws);
-    inv = view_bytes(inv, vws);
     weights = view_bytes(weights, vws);
     bits = view_bytes(bits, vws);
     colcnt = view_bytes(colcnt, vws);
@@ -416,9 +415,8 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
 #pragma unroll
     for (int j = 0; j < SETUP_PER_THREAD; ++j) {
         const int p = p0 + j * SETUP_NT + threadIdx.x;
-        const int id = p < n ? sorted_ids[p] : -1;
-        if ((unsigned)id < (unsigned)n) inv[id] = p;    // sorted position by id, for the backward
-        ids[j] = (p < nvis && (unsigned)id < (unsigned)n) ? id : -1;
+        const int id = p < nvis ? sorted_ids[p] : -1;
+        ids[j] = (unsigned)id < (unsigned)n ? id : -1;
     }
     IdRec q[SETUP_PER_THREAD];
 #pragma unroll
@@ -433,7 +431,7 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
         uint2 rr = make_uint2(NO_TILE_X, 0u);
         if (p < n && ids[j] >= 0 && q[j].rect.x != NO_TILE_X) {
             Rec r = q[j].r;
-            r.c.w = (uint32_t)p;
+            r.c.w = (uint32_t)ids[j];  // the splat's gradient slot
             rec[p] = r;
             rr = q[j].rect;
         }
@@ -672,9 +670,11 @@ __device__ __forceinline__ void scan_round(Walk<RC>& w, const uint2* __restrict_
 }
 
 // Stages hits [b0, b0 + BATCH) of the round (in order across the four waves' lists).
+// The record's c.w is the splat id, which names its gradient slot: clamped to [0, n), so that a
+// setup that does not belong to these inputs gives wrong gradients but no access out of bounds.
 template <int RC>
-__device__ __forceinline__ void stage(Walk<RC>& w, const Rec* __restrict__ rec, int b0, int total,
-                                      int tid) {
+__device__ __forceinline__ void stage(Walk<RC>& w, const Rec* __restrict__ rec, int n, int b0,
+                                      int total, int tid) {
     const int e = b0 + tid;
     if (e < total) {
         int off = e, ws = 0;
@@ -688,7 +688,7 @@ __device__ __forceinline__ void stage(Walk<RC>& w, const Rec* __restrict__ rec, 
         const uint32_t v = w.seg[ws][off];
         const int pos = w.chunk[v / CHUNK_SPLATS] * CHUNK_SPLATS + (int)(v % CHUNK_SPLATS);
         Rec r = rec[pos];
-        r.c.w = (uint32_t)pos;      // the gradient slot comes from the walk, never from memory
+        r.c.w = min(r.c.w, (uint32_t)(n - 1));
         w.rec[tid] = r;
     }
 }
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         if (INSTR) { nq += total; nchk += w.nchunk; nbat += (total + BATCH - 1) / BATCH; }
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
-            stage(w, rec, b0, total, tid);
+            stage(w, rec, n, b0, total, tid);
             __syncthreads();
             const int m = min(BATCH, total - b0);
             if (!TCULL || alive) {
@@ -1156,7 +1156,7 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
             if (tile_acc) { flush_tile_grad<INSTR>(tg, w, pend, tid, grad, cnt); pend = 0; }
-            stage(w, rec, b0, total, tid);
+            stage(w, rec, n, b0, total, tid);
             __syncthreads();
             const int m = min(BATCH, total - b0);
             pend = m;
@@ -1338,16 +1338,13 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     }
 }
 
-// The accumulated gradients moved from sorted position to splat id, one thread per id: it
-// gathers its splat's slot (found through the setup's inverse permutation) and writes the
-// outputs in id order; zero for culled splats.
+// The accumulated gradients from their slots (one per splat id, cleared before the backward, so
+// zero for culled splats) to the output arrays, one thread per id, both read and written in id
+// order.
 __global__ __launch_bounds__(256) void k_grad_finalize(
-    int n, const int32_t* __restrict__ inv, const int32_t* __restrict__ nvis_ptr,
-    const float* __restrict__ grad, const float* __restrict__ rgb, int saturate,
+    int n, const float* __restrict__ grad, const float* __restrict__ rgb, int saturate,
     float* __restrict__ g_m, float* __restrict__ g_c, float* __restrict__ g_o,
     float* __restrict__ g_rgb, uint64_t vws) {
-    inv = view_bytes(inv, vws);
-    nvis_ptr = view_at(nvis_ptr, 1);
     grad = view_bytes(grad, vws);
     rgb = view_at(rgb, 3ull * n);
     g_m = view_at(g_m, 2ull * n);
@@ -1356,22 +1353,15 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
     g_rgb = view_at(g_rgb, 3ull * n);
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n) return;
-    int nvis = *nvis_ptr;
-    nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
-    const int p = inv[id];
     float v[9];
-    if ((unsigned)p < (unsigned)nvis) {
-        const float4* gp = reinterpret_cast<const float4*>(grad + (size_t)p * GRAD_STRIDE);
-        const float4 u0 = gp[0], u1 = gp[1];
-        const float u2 = grad[(size_t)p * GRAD_STRIDE + 8];
-        v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
-        v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w; v[8] = u2;
-        if (saturate)
-            for (int ch = 0; ch < 3; ++ch)
-                if (rgb[3 * (size_t)id + ch] > 1.f) v[6 + ch] = 0.f;
-    } else {
-        for (int j = 0; j < 9; ++j) v[j] = 0.f;
-    }
+    const float4* gp = reinterpret_cast<const float4*>(grad + (size_t)id * GRAD_STRIDE);
+    const float4 u0 = gp[0], u1 = gp[1];
+    const float u2 = grad[(size_t)id * GRAD_STRIDE + 8];
+    v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+    v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w; v[8] = u2;
+    if (saturate)
+        for (int ch = 0; ch < 3; ++ch)
+            if (rgb[3 * (size_t)id + ch] > 1.f) v[6 + ch] = 0.f;
     g_m[2 * (size_t)id] = v[0];
     g_m[2 * (size_t)id + 1] = v[1];
     g_c[3 * (size_t)id] = v[2];
@@ -1427,7 +1417,7 @@ static bool split_ok(int n, int width, int height) {
 size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
     const size_t nt = (size_t)tiles_of(width, height);
     const size_t wpr = (size_t)bitmap_wpr(n, width, height);
-    size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) + align_up((size_t)n * 4) +
+    size_t b = align_up((size_t)n * REC_BYTES) + align_up((size_t)n * 8) +
                align_up(16 * 8) + align_up(nt * 4) * 4 + align_up(nt * wpr * 4);
     if (split_ok(n, width, height))
         b += align_up(nt * (wpr / COL_WORDS) * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
@@ -1447,7 +1437,6 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     char* p = (char*)ws;
     r.rec = p;      p += align_up((size_t)n * REC_BYTES);
     r.rect = p;     p += align_up((size_t)n * 8);
-    r.inv = (int32_t*)p; p += align_up((size_t)n * 4);
     r.counters = (unsigned long long*)p; p += align_up(16 * 8);
     r.weights = (uint32_t*)p; p += align_up(nt * 4);
     r.order = (int32_t*)p;    p += align_up(nt * 4);
@@ -1497,9 +1486,9 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
         const size_t lds =
             ntiles <= MAX_LDS_TILES ? ((size_t)ntiles * COL_WORDS + (ntiles + 1) / 2) * 4 : 0;
         hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V),
-                           dim3(SETUP_NT), lds, s, n, sorted_ids, n_visible, (const IdRec*)r.idrec, tiles_x, ntiles,
-                           (Rec*)r.rec, (uint2*)r.rect, r.inv, r.weights, r.bits, r.wpr, r.colcnt,
-                           vs.ws);
+                           dim3(SETUP_NT), lds, s, n, sorted_ids, n_visible,
+                           (const IdRec*)r.idrec, tiles_x, ntiles, (Rec*)r.rec, (uint2*)r.rect,
+                           r.weights, r.bits, r.wpr, r.colcnt, vs.ws);
     }
     hipLaunchKernelGGL(k_plan_tiles, dim3(1, V), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
                        r.split, r.tile_k, r.tile_first, r.counters, r.bwd_w, vs.ws);
@@ -1655,9 +1644,8 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
         if (e != hipSuccess) return e;
     }
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256, V), dim3(256), 0, s, n,
-                       (const int32_t*)r.inv, n_visible, r.grad, rgb, sat, g_means2d, g_conics,
-                       g_opac, g_rgb, vs.ws);
+    hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256, V), dim3(256), 0, s, n, r.grad, rgb,
+                       sat, g_means2d, g_conics, g_opac, g_rgb, vs.ws);
     return hipGetLastError();
 }
 
