@@ -26,6 +26,7 @@ namespace gsr {
 
 constexpr int NT = 256;            // threads per workgroup
 constexpr int BATCH = 256;         // splat records staged in LDS at once
+static_assert(BATCH == NT, "staging and the tile gradient flush give each thread one record");
 
 // A staged splat: a = (mean x, mean y, a', k); b = (d', opacity, r, g);
 // c = (bits of colour b, bits of log2 o, bits of p_min, splat id) where p_min = log2(alpha_min / o)
@@ -1038,27 +1039,34 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
     }
 }
 
-// GS_REDUCE_TILE: thread t owns entry t of the staged batch's LDS accumulator; it adds the
-// entry to the splat's gradient slot (one set of global atomics per splat and tile) and clears it.
-// Called before entry t is restaged and once after the walk.
+// GS_REDUCE_TILE: adds the staged batch's LDS accumulator (9 sums per entry) to the splats'
+// gradient slots, one set of global atomics per splat and tile, and clears it. Thread t takes
+// values t, t + NT, ..., so consecutive lanes add consecutive values of a slot and one wave's
+// atomics touch about 7 slots' cache lines instead of 64. Reads other entries' records: the caller
+// waits at a barrier before restaging them. Called before each restage and once after the walk.
 template <bool INSTR, int RC>
 __device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Walk<RC>& w,
                                                 int pend, int tid, float* __restrict__ grad,
                                                 BwdCounts& cnt) {
-    if (tid < pend) {
-        float v[9];
+    if (INSTR) {                                  // sets committed: entries with a non-zero sum
         bool any = false;
-#pragma unroll
-        for (int j = 0; j < 9; ++j) { v[j] = tg[tid * 9 + j]; any = any || v[j] != 0.f; }
-        if (any) {
-            float* gp = grad + (size_t)w.rec[tid].c.w * GRAD_STRIDE;
-#pragma unroll
-            for (int j = 0; j < 9; ++j) atomic_add_f32(gp + j, v[j]);
-            if (INSTR) cnt.sets += 1;
-        }
+        if (tid < pend)
+            for (int j = 0; j < 9; ++j) any = any || tg[tid * 9 + j] != 0.f;
+        cnt.sets += any;
+        __syncthreads();                          // before any value below is cleared
     }
-#pragma unroll
-    for (int j = 0; j < 9; ++j) tg[tid * 9 + j] = 0.f;
+#pragma unroll 1
+    for (int k = 0; k < 9; ++k) {
+        const int q = tid + k * NT;               // value q: entry q / 9, gradient q % 9
+        if (q < pend * 9) {
+            const float v = tg[q];
+            if (v != 0.f) {
+                const int e = q / 9;
+                atomic_add_f32(grad + (size_t)w.rec[e].c.w * GRAD_STRIDE + (q - 9 * e), v);
+            }
+        }
+        tg[q] = 0.f;
+    }
 }
 
 // TILEM: an instance for GS_REDUCE_TILE alone, without the per-fragment reduction paths of the
@@ -1155,7 +1163,11 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
         if (INSTR) nq += total;
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
-            if (tile_acc) { flush_tile_grad<INSTR>(tg, w, pend, tid, grad, cnt); pend = 0; }
+            if (tile_acc) {
+                flush_tile_grad<INSTR>(tg, w, pend, tid, grad, cnt);
+                pend = 0;
+                __syncthreads();                  // the flush read other threads' records
+            }
             stage(w, rec, n, b0, total, tid);
             __syncthreads();
             const int m = min(BATCH, total - b0);
