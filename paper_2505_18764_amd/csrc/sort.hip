@@ -1,10 +1,11 @@
 // sort.hip -- stable LSD radix sort of (key, int32 value) pairs with the sort length read on
 // the device (the depth sort of Sec. 1 and Sec. 4.1, dynamic length after frustum culling).
 //
-// Each 8-bit digit pass: (1) per-block digit histograms, (2) one exclusive scan over the
-// digit-major [digit][block] table, (3) a stable scatter in which every block ranks its keys
-// round by round (256 keys per round, one per thread, in input order), ranking equal digits
-// inside a wave with eight ballots and across the four waves through LDS counts.
+// Each 8-bit digit pass: (1) per-block digit histograms, (2) per digit, an exclusive scan of its
+// counts over the blocks and the digit's total, (3) a stable scatter in which every block first
+// scans the 256 digit totals into digit bases, then ranks its keys round by round (256 keys per
+// round, one per thread, in input order), ranking equal digits inside a wave with eight ballots
+// and across the four waves through LDS counts. Three launches per pass.
 // Several views sort in one launch per step (grid y = view): each view's keys, ids and count are
 // its part of [V][n] arrays, and its histograms and ping-pong buffers live in its workspace slab.
 #include "device.hpp"
@@ -199,24 +200,78 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t count
     return hipGetLastError();
 }
 
+// Row d of the digit-major [digit][block] count table (one workgroup per digit): the exclusive
+// prefix of each block within the digit, and the digit's total.
+__global__ __launch_bounds__(256) void k_digit_scan(const uint32_t* __restrict__ hist,
+                                                    int nblocks, uint32_t* __restrict__ prefix,
+                                                    uint32_t* __restrict__ totals, uint64_t vws) {
+    __shared__ uint32_t s_w[4];
+    hist = view_bytes(hist, vws);
+    prefix = view_bytes(prefix, vws);
+    totals = view_bytes(totals, vws);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
+    uint32_t* orow = prefix + (size_t)blockIdx.x * nblocks;
+    uint32_t carry = 0u;
+    for (int b0 = 0; b0 < nblocks; b0 += 256) {     // 256 blocks' counts at a time
+        const int b = b0 + tid;
+        const uint32_t v = b < nblocks ? row[b] : 0u;
+        uint32_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t before = carry, chunk = 0u;
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2) {
+            before += w2 < wave ? s_w[w2] : 0u;
+            chunk += s_w[w2];
+        }
+        __syncthreads();                            // s_w is rewritten by the next chunk
+        if (b < nblocks) orow[b] = before + incl - v;
+        carry += chunk;
+    }
+    if (tid == 0) totals[blockIdx.x] = carry;
+}
+
 template <typename K>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     const K* __restrict__ kin, const int32_t* __restrict__ vin, int in_ws, K* __restrict__ kout,
     int32_t* __restrict__ vout, int out_ws, int n_max, const int32_t* __restrict__ n_dev,
-    int shift, int nblocks, const uint32_t* __restrict__ offsets, uint64_t vws) {
+    int shift, int nblocks, const uint32_t* __restrict__ prefix,
+    const uint32_t* __restrict__ totals, uint64_t vws) {
     __shared__ uint32_t s_off[256];
     __shared__ uint16_t s_cnt[2][4][256];
+    __shared__ uint32_t s_w[4];
     kin = sort_buf(kin, in_ws, n_max, vws);
     vin = sort_buf(vin, in_ws, n_max, vws);
     kout = sort_buf(kout, out_ws, n_max, vws);
     vout = sort_buf(vout, out_ws, n_max, vws);
     n_dev = view_at(n_dev, 1);
-    offsets = view_bytes(offsets, vws);
+    prefix = view_bytes(prefix, vws);
+    totals = view_bytes(totals, vws);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = dev_count(n_dev, n_max);
     const int start = blockIdx.x * SORT_ITEMS;
     if (start >= n) return;                         // uniform for the block
-    s_off[tid] = offsets[(size_t)tid * nblocks + blockIdx.x];
+    {   // thread tid owns digit tid: its base is the exclusive scan of the digit totals
+        const uint32_t t = totals[tid];
+        uint32_t incl = t;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        uint32_t base = incl - t;
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2) base += w2 < wave ? s_w[w2] : 0u;
+        s_off[tid] = base + prefix[(size_t)tid * nblocks + blockIdx.x];
+    }
     for (int b = 0; b < 2; ++b)
         for (int w = 0; w < 4; ++w) s_cnt[b][w][tid] = 0;
     __syncthreads();
@@ -369,9 +424,8 @@ static int sort_blocks(int n) { return (n + SORT_ITEMS - 1) / SORT_ITEMS; }
 size_t sort_ws_bytes(int n, int key_bytes) {
     const size_t nb = (size_t)(n > 0 ? sort_blocks(n) : 1);
     const size_t table = 256 * nb;
-    const size_t sums = (table + SCAN_ITEMS - 1) / SCAN_ITEMS;
     return align_up((size_t)n * key_bytes) + align_up((size_t)n * 4) + align_up(table * 4) * 2 +
-           align_up(sums * 4);
+           align_up(256 * 4);
 }
 
 template <typename K>
@@ -386,8 +440,7 @@ static hipError_t sort_pairs(int n, K* keys, int32_t* vals, const int32_t* n_dev
     int32_t* valt = (int32_t*)p; p += align_up((size_t)n * 4);
     uint32_t* hist = (uint32_t*)p; p += align_up(table * 4);
     uint32_t* offs = (uint32_t*)p; p += align_up(table * 4);
-    uint32_t* sums = (uint32_t*)p;
-    if ((table + SCAN_ITEMS - 1) / SCAN_ITEMS > 1024 * 64) return hipErrorInvalidValue;
+    uint32_t* totals = (uint32_t*)p;
     K* kin = keys; int32_t* vin = vals;
     K* kout = kalt; int32_t* vout = valt;
     int in_ws = 0, out_ws = 1;
@@ -395,10 +448,10 @@ static hipError_t sort_pairs(int n, K* keys, int32_t* vals, const int32_t* n_dev
     for (int shift = 0; shift < end_bit; shift += 8, ++passes) {
         hipLaunchKernelGGL(k_sort_hist<K>, dim3(nb, V), dim3(SORT_THREADS), 0, s, kin, in_ws, n,
                            n_dev, shift, nb, hist, vs.ws);
-        hipError_t e = launch_exclusive_scan(hist, offs, table, sums, s, vs);
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_digit_scan, dim3(256, V), dim3(256), 0, s, hist, nb, offs, totals,
+                           vs.ws);
         hipLaunchKernelGGL(k_sort_scatter<K>, dim3(nb, V), dim3(SORT_THREADS), 0, s, kin, vin,
-                           in_ws, kout, vout, out_ws, n, n_dev, shift, nb, offs, vs.ws);
+                           in_ws, kout, vout, out_ws, n, n_dev, shift, nb, offs, totals, vs.ws);
         K* tk = kin; kin = kout; kout = tk;
         int32_t* tv = vin; vin = vout; vout = tv;
         const int tw = in_ws; in_ws = out_ws; out_ws = tw;
