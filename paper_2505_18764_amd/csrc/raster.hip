@@ -333,14 +333,20 @@ struct IdRec {
 };
 static_assert(sizeof(IdRec) == 64, "one cache line per splat");
 
+// Also clears the tile weights (the first workgroup; k_raster_setup adds to them after it).
 __global__ __launch_bounds__(256) void k_raster_pack(
     int n, const float* __restrict__ means2d, const float* __restrict__ conics,
     const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
-    int saturate, IdRec* __restrict__ out, uint64_t vws) {
+    int saturate, IdRec* __restrict__ out, uint32_t* __restrict__ weights, int ntiles,
+    uint64_t vws) {
     means2d = view_at(means2d, 2ull * n);
     conics = view_at(conics, 3ull * n);
     rgb = view_at(rgb, 3ull * n);          // opacities are the views' shared [n]
     out = view_bytes(out, vws);
+    if (blockIdx.x == 0) {
+        weights = view_bytes(weights, vws);
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) weights[t] = 0u;
+    }
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const float mx = means2d[2 * (size_t)id], my = means2d[2 * (size_t)id + 1];
@@ -1488,13 +1494,14 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
     const int tiles_x = (width + TILE - 1) / TILE;
     const int ntiles = tiles_of(width, height);
     const int V = vs.count;
-    hipError_t e = launch_fill_u32(r.weights, (size_t)ntiles, 0u, s, V, vs.ws);
-    if (e != hipSuccess) return e;
-    if (n > 0) {
+    if (n == 0) {
+        hipError_t e = launch_fill_u32(r.weights, (size_t)ntiles, 0u, s, V, vs.ws);
+        if (e != hipSuccess) return e;
+    } else {
         const int sat = (cfg.fb_format == FB_UNORM16 || cfg.fb_format == FB_UNORM8) ? 1 : 0;
         hipLaunchKernelGGL(k_raster_pack, dim3((n + 255) / 256, V), dim3(256), 0, s, n, means2d,
                            conics, opac, rgb, width, height, cfg.alpha_min, sat, (IdRec*)r.idrec,
-                           vs.ws);
+                           r.weights, ntiles, vs.ws);
         const size_t lds =
             ntiles <= MAX_LDS_TILES ? ((size_t)ntiles * COL_WORDS + (ntiles + 1) / 2) * 4 : 0;
         hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V),
