@@ -815,7 +815,9 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                 // from its lane by readlane (no LDS round trip per entry)
                 for (int i0 = 0; i0 < nlist; i0 += 64) {
                     const int ents = i0 + lane < nlist ? (int)w.list[wave][i0 + lane] : 0;
-                    const int iend = min(64, nlist - i0);
+                    // a scalar bound: as a min the compiler forms it as a vector median and spends
+                    // two VALU operations per entry on the loop test
+                    const int iend = __builtin_amdgcn_readfirstlane(min(64, nlist - i0));
                     for (int i = 0; i < iend; ++i) {
                         const uint32_t ent = (uint32_t)__builtin_amdgcn_readlane(ents, i);
                         const int k = (int)(ent & 0xFFu);
@@ -1182,7 +1184,7 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
             // the list is read 64 entries at a time, one per lane (readlane takes each entry)
             for (int i0 = 0; i0 < nlist && alive; i0 += 64) {
                 const int ents = i0 + lane < nlist ? (int)w.list[wave][i0 + lane] : 0;
-                const int iend = min(64, nlist - i0);
+                const int iend = __builtin_amdgcn_readfirstlane(min(64, nlist - i0));
                 for (int i = 0; i < iend && alive; ++i) {
                     const uint32_t ent = (uint32_t)__builtin_amdgcn_readlane(ents, i);
                     const int k = (int)(ent & 0xFFu);
