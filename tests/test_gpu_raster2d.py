@@ -79,6 +79,15 @@ def test_cfg1_parity_all_reduce_modes(mode):
     st = out["stats"]
     assert st["bwd_live"] == out["live"].sum()
     assert st["fwd_covered"] == out["cov"].sum()
+    # the forward walk's counters bound one another: every staged (tile, splat) pair lies in a
+    # tested 16-splat chunk and in a staged batch of at most 256; each enters at most one culled
+    # list per wave (4 per tile); each list entry evaluates at most 4 sub-blocks of 64 pixels
+    assert st["fwd_queued"] <= 16 * st["fwd_chunks"]
+    assert st["fwd_queued"] <= 256 * st["fwd_batches"]
+    assert st["fwd_walked"] <= 4 * st["fwd_queued"]
+    assert st["fwd_covered"] <= st["fwd_evaluated"] <= 256 * st["fwd_walked"]
+    assert st["fwd_empty_blocks"] <= 4 * st["fwd_walked"]
+    assert st["fwd_walked"] > 0 and st["fwd_covered"] > 0
     if mode == "naive":
         assert st["bwd_atomic_sets"] == st["bwd_live"]       # atomic-add rate 1.000 (Table 1)
     else:
