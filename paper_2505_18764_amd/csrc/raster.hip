@@ -1358,13 +1358,43 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     }
 }
 
+// dL/dbackground: the tiles' partial sums of every view added in a fixed order by one workgroup
+// of 256 threads (all of them call it).
+__device__ void bg_reduce(int ntiles, int nviews, const float* __restrict__ bgpart, uint64_t vws,
+                          float* __restrict__ out) {
+    __shared__ float s[3][256];
+    float a[3] = {0.f, 0.f, 0.f};
+    for (int v = 0; v < nviews; ++v) {
+        const float* bp = reinterpret_cast<const float*>(
+            reinterpret_cast<uintptr_t>(bgpart) + (uint64_t)v * vws);
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
+            for (int c = 0; c < 3; ++c) a[c] += bp[(size_t)t * 4 + c];
+    }
+    for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = a[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int c = 0; c < 3; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_bg_reduce(int ntiles, int nviews,
+                                                   const float* __restrict__ bgpart, uint64_t vws,
+                                                   float* __restrict__ out) {
+    bg_reduce(ntiles, nviews, bgpart, vws, out);
+}
+
 // The accumulated gradients from their slots (one per splat id, cleared before the backward, so
 // zero for culled splats) to the output arrays, one thread per id, both read and written in id
-// order.
+// order. With `dbg`, the first workgroup also reduces dL/dbackground (bg_reduce).
 __global__ __launch_bounds__(256) void k_grad_finalize(
     int n, const float* __restrict__ grad, const float* __restrict__ rgb, int saturate,
     float* __restrict__ g_m, float* __restrict__ g_c, float* __restrict__ g_o,
-    float* __restrict__ g_rgb, uint64_t vws) {
+    float* __restrict__ g_rgb, uint64_t vws, int ntiles, int nviews,
+    const float* __restrict__ bgpart, float* __restrict__ dbg) {
+    if (dbg && blockIdx.x == 0 && blockIdx.y == 0) bg_reduce(ntiles, nviews, bgpart, vws, dbg);
     grad = view_bytes(grad, vws);
     rgb = view_at(rgb, 3ull * n);
     g_m = view_at(g_m, 2ull * n);
@@ -1395,27 +1425,6 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
 
 // dL/dbackground: the per-tile partial sums of every view, added in a fixed order
 // (deterministic). The background is one colour shared by the views, so its gradient is their sum.
-__global__ __launch_bounds__(256) void k_bg_reduce(int ntiles, int nviews,
-                                                   const float* __restrict__ bgpart, uint64_t vws,
-                                                   float* __restrict__ out) {
-    __shared__ float s[3][256];
-    float a[3] = {0.f, 0.f, 0.f};
-    for (int v = 0; v < nviews; ++v) {
-        const float* bp = reinterpret_cast<const float*>(
-            reinterpret_cast<uintptr_t>(bgpart) + (uint64_t)v * vws);
-        for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
-            for (int c = 0; c < 3; ++c) a[c] += bp[(size_t)t * 4 + c];
-    }
-    for (int c = 0; c < 3; ++c) s[c][threadIdx.x] = a[c];
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int c = 0; c < 3; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
-}
-
 // ---- host side -------------------------------------------------------------------------------
 
 static int tiles_of(int width, int height) {
@@ -1658,15 +1667,15 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                        vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (dL_dbg) {
-        hipLaunchKernelGGL(k_bg_reduce, dim3(1), dim3(256), 0, s, nblocks, V,
-                           (const float*)r.bgpart, vs.ws, dL_dbg);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    if (n == 0) {                        // no gradients to finalise: the background alone
+        if (dL_dbg)
+            hipLaunchKernelGGL(k_bg_reduce, dim3(1), dim3(256), 0, s, nblocks, V,
+                               (const float*)r.bgpart, vs.ws, dL_dbg);
+        return hipGetLastError();
     }
-    if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_grad_finalize, dim3((n + 255) / 256, V), dim3(256), 0, s, n, r.grad, rgb,
-                       sat, g_means2d, g_conics, g_opac, g_rgb, vs.ws);
+                       sat, g_means2d, g_conics, g_opac, g_rgb, vs.ws, nblocks, V,
+                       (const float*)r.bgpart, dL_dbg);
     return hipGetLastError();
 }
 
