@@ -420,3 +420,117 @@ def test_background_and_dLdT_finite_differences():
     fd, an = np.array(fd), np.array(an)
     assert len(fd) >= 50
     assert np.abs(fd - an).max() <= 1e-6 * np.linalg.norm(an), (np.abs(fd - an).max(), np.linalg.norm(an))
+
+
+# ---- per-fragment format emulation, by hand -------------------------------------------------
+# A render target that blends in its own format rounds the stored state after every fragment
+# (Sec. 3.3). For uniform slabs (zero conic, alpha = o at every pixel) the whole computation of
+# one pixel is written out below in numpy, store by store, in the order of Eq. 2 / Eq. 5 for the
+# forward and Procedure 1 (Eqs. 3, 7, then the Eqs. 6 and 5 stores) for the backward, with the
+# format's rounding taken from numpy (float16) or the unorm definition. Rounding placed before
+# the C' update, or applied to C' but not to T, or skipped at the backward's stores, gives other
+# numbers; the test checks that each such variant differs from the oracle.
+
+def _round_np(x, fmt):
+    if fmt == "f16":
+        return float(np.float16(x))                      # numpy rounds double -> half (RNE)
+    if fmt == "unorm16":
+        return float(np.rint(min(max(x, 0.0), 1.0) * 65535.0) / 65535.0)
+    raise ValueError(fmt)
+
+
+def _slab_pixel_by_hand(ops, cols, G, fmt, t_min_bwd=0.0, variant=None):
+    """Image, T, dL/dalpha and dL/dc of one pixel over uniform slabs, per-fragment rounding."""
+    rnd = lambda x: _round_np(x, fmt)
+    C, T = [0.0, 0.0, 0.0], 1.0
+    for o, c in zip(ops, cols):
+        C = [rnd(C[ch] + T * o * c[ch]) for ch in range(3)]          # C += T alpha c, stored
+        T = rnd(T * (1.0 - o))                                        # T (1 - alpha), stored
+    C = [rnd(x) for x in C]                                           # written back at rest
+    ga, gc = [], []
+    Cp, Tb = list(C), 1.0                                             # (C'_1, T_1) = (C, 1)
+    for o, c in zip(ops, cols):
+        if Tb < t_min_bwd:                                            # T-culled: state frozen
+            ga.append(0.0)
+            gc.append([0.0, 0.0, 0.0])
+            continue
+        gc.append([G[ch] * o * Tb for ch in range(3)])                # Eq. 3
+        s = 0.0
+        if variant == "round_before_update":
+            Cp = [rnd(x) for x in Cp]
+        for ch in range(3):
+            s += G[ch] * (c[ch] * Tb - Cp[ch])                        # Eq. 7 numerator
+        ga.append(s / (1.0 - o))
+        if variant == "no_backward_rounding":
+            Cp = [Cp[ch] - Tb * o * c[ch] for ch in range(3)]
+            Tb = Tb * (1.0 - o)
+        elif variant == "no_T_rounding":
+            Cp = [rnd(Cp[ch] - Tb * o * c[ch]) for ch in range(3)]
+            Tb = Tb * (1.0 - o)
+        elif variant == "round_before_update":
+            Cp = [Cp[ch] - Tb * o * c[ch] for ch in range(3)]
+            Tb = Tb * (1.0 - o)
+        else:
+            Cp = [rnd(Cp[ch] - Tb * o * c[ch]) for ch in range(3)]   # Eq. 6, stored
+            Tb = rnd(Tb * (1.0 - o))                                  # Eq. 5, stored
+    return np.array(C), T, np.array(ga), np.array(gc)
+
+
+_SLAB_CASES = {
+    "one": ([0.37], [[0.8173, 0.2291, 0.5519]]),
+    "two": ([0.37, 0.61], [[0.8173, 0.2291, 0.5519], [0.1367, 0.9042, 0.4433]]),
+    "five": ([0.37, 0.61, 0.23, 0.52, 0.44],
+             [[0.8173, 0.2291, 0.5519], [0.1367, 0.9042, 0.4433], [0.6711, 0.3105, 0.0917],
+              [0.2468, 0.7531, 0.9876], [0.5050, 0.4049, 0.3048]]),
+}
+
+
+@pytest.mark.parametrize("fmt", ["f16", "unorm16"])
+@pytest.mark.parametrize("case", list(_SLAB_CASES))
+def test_per_fragment_emulation_by_hand(fmt, case):
+    ops, cols = _SLAB_CASES[case]
+    K = len(ops)
+    G = np.array([0.7, -1.3, 0.25])
+    Gimg = np.broadcast_to(G[:, None, None], (3, 1, 1)).copy()
+    cfg = _cfg(prefilter=False, t_min_bwd=0.0, fb_format=fmt, emulate=True,
+               fb_round="per_fragment")
+    out = oracle.raster(**_slabs(ops, cols), order=np.arange(K), width=1, height=1,
+                        dL_dimg=Gimg, cfg=cfg)
+    C, T, ga, gc = _slab_pixel_by_hand(ops, cols, G, fmt)
+    np.testing.assert_array_equal(out["img"][:, 0, 0], C)
+    assert out["T"][0, 0] == T
+    # opacity gradient = dL/dalpha (exp(-q/2) = 1 on a slab); colour gradient = Eq. 3
+    np.testing.assert_allclose(out["grad"][:, 5], ga, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(out["grad"][:, 6:9], gc, rtol=1e-15, atol=0)
+    # the rounding is really there: the plain FP64 result differs by about a format step
+    plain = oracle.raster(**_slabs(ops, cols), order=np.arange(K), width=1, height=1,
+                          dL_dimg=Gimg, cfg=_cfg(prefilter=False, t_min_bwd=0.0))
+    assert np.abs(plain["img"][:, 0, 0] - C).max() > 0
+    # every misplaced rounding gives other numbers, so the comparison above would catch it
+    for v in ("round_before_update", "no_T_rounding", "no_backward_rounding"):
+        _, _, ga_v, _ = _slab_pixel_by_hand(ops, cols, G, fmt, variant=v)
+        if K > 1:
+            assert np.abs(ga_v - out["grad"][:, 5]).max() > 1e-9, v
+
+
+@pytest.mark.parametrize("fmt", ["f16", "unorm16"])
+def test_per_fragment_emulation_with_tcull(fmt):
+    """Twenty slabs of opacity 0.45: the rounded T crosses 1e-4 at a fragment the hand model
+    finds, the later fragments are culled (Procedure 1), and every live fragment's dL/dalpha is
+    the hand value."""
+    K, o = 20, 0.45
+    cols = [[0.2 + 0.03 * k, 0.9 - 0.04 * k, 0.5] for k in range(K)]
+    G = np.array([0.4, 0.9, -0.6])
+    Gimg = np.broadcast_to(G[:, None, None], (3, 1, 1)).copy()
+    tb = float(np.float32(1e-4))
+    cfg = _cfg(prefilter=False, t_min_bwd=tb, fb_format=fmt, emulate=True,
+               fb_round="per_fragment")
+    out = oracle.raster(**_slabs([o] * K, cols), order=np.arange(K), width=1, height=1,
+                        dL_dimg=Gimg, cfg=cfg)
+    C, T, ga, gc = _slab_pixel_by_hand([o] * K, cols, G, fmt, t_min_bwd=tb)
+    live = int((ga != 0.0).sum())
+    assert 5 < live < K and out["live"][0, 0] == live
+    np.testing.assert_array_equal(out["img"][:, 0, 0], C)
+    assert out["T"][0, 0] == T
+    np.testing.assert_allclose(out["grad"][:, 5], ga, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(out["grad"][:, 6:9], gc, rtol=1e-15, atol=0)
