@@ -14,7 +14,8 @@
  *     (FP32 unless typed otherwise). The library never allocates device memory; scratch comes from
  *     the caller's workspace `ws` of `ws_bytes` bytes (size it with gs_workspace_size()).
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Work is enqueued
- *     asynchronously; no entry point synchronises the device or the stream.
+ *     asynchronously; no entry point synchronises the device or the stream, except
+ *     gs_raster_status, which waits for its stream to read the device status word back.
  *   - Arguments are validated on the host before any HIP call. On failure the call returns a
  *     nonzero status, enqueues nothing, and gs_last_error() describes the problem (thread-local).
  *     GS_ERR_HIP means a launch failed; its message carries the HIP error string.
@@ -56,7 +57,19 @@ enum gs_status {
     GS_ERR_INVALID_ARGUMENT = 1,
     GS_ERR_CAPACITY = 2,        /* workspace or pair buffer too small */
     GS_ERR_UNSUPPORTED = 3,
-    GS_ERR_HIP = 4
+    GS_ERR_HIP = 4,
+    GS_ERR_STATE = 5            /* gs_raster_status: a kernel found inconsistent state (see below) */
+};
+
+/* Bits of the raster's device status word (gs_raster_status). Each names an input or workspace
+ * state the kernels refuse to guess about; the affected work is skipped, so the outputs of the
+ * calls since the last raster setup are then incomplete. */
+enum gs_status_bits {
+    GS_STATUS_BAD_ID = 1,           /* sorted_ids[p] outside 0..n-1 for some p < n_visible */
+    GS_STATUS_FWD_SCHEDULE = 2,     /* the forward met a tile or work-item entry outside its range */
+    GS_STATUS_BWD_SCHEDULE = 4,     /* the backward met a tile entry outside its range */
+    GS_STATUS_STALE_RECORD = 8      /* a staged record named a splat outside 0..n-1: the workspace
+                                       holds a setup built for other inputs */
 };
 
 /* Render-target formats of the framebuffer state (Sec. 3.3, mixed-precision rendering). */
@@ -322,6 +335,37 @@ int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n,
                       const float* dL_dopacities2d,
                       float* dL_dmeans3d, float* dL_dscales, float* dL_dquats,
                       float* dL_dopacities, float* dL_dsh, void* stream);
+
+/*
+ * The raster's device status word: every raster setup (gs_raster_setup, or a gs_raster_fwd /
+ * gs_raster_bwd that builds its own) clears it, and the setup, forward and backward kernels set
+ * gs_status_bits in it when they meet a splat id or a schedule entry outside its range, instead
+ * of substituting a value. This call waits for `stream`, copies the word of each of the
+ * cfg->n_views workspace slabs to the host, and stores their OR in *status (host pointer).
+ * Returns GS_OK when it is zero and GS_ERR_STATE otherwise (gs_last_error() names the bits).
+ * n, width, height and cfg must be those of the raster calls that used the workspace.
+ * Unlike every other entry point it synchronises (the stream only).
+ */
+int gs_raster_status(const gs_config* cfg, int32_t n, int32_t width, int32_t height,
+                     const void* ws, size_t ws_bytes, uint32_t* status, void* stream);
+
+/*
+ * Diagnostics: copies the raster's schedules from the workspace into caller device buffers
+ * (enqueued on `stream`, no synchronisation). With T = tiles of 32 x 32 pixels of the image and
+ * V = cfg->n_views (each buffer holds V views back to back):
+ *   fwd_order [V][T] int32   tiles in the forward's dispatch order (one tile per workgroup);
+ *   bwd_order [V][T] int32   tiles in the backward's dispatch order (written by gs_raster_bwd);
+ *   item_order [V][4T] int32 the depth-split forward's work items in dispatch order, -1 past the
+ *                            item count; items [V][4T] int4 (tile, first column, end column,
+ *                            partial slot or -1); n_items [V] int64 the item count.
+ * Each pointer may be NULL. The item arrays exist only when the workspace holds a depth split
+ * (GS_ERR_UNSUPPORTED if item_order, items or n_items is requested without one: images of more
+ * than 4096 tiles). A setup (or forward) must have run on the workspace first.
+ */
+int gs_raster_debug_schedule(const gs_config* cfg, int32_t n, int32_t width, int32_t height,
+                             const void* ws, size_t ws_bytes, int32_t* fwd_order,
+                             int32_t* bwd_order, int32_t* item_order, int32_t* items,
+                             int64_t* n_items, void* stream);
 
 /* ---- Comparison design: tile-based software rasterization (Sec. 2.1.3-2.1.4) ----------------
  *

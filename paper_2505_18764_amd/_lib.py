@@ -24,7 +24,9 @@ REDUCE_MODES = {"naive": 0, "quad": 1, "wave": 2, "hybrid": 3, "hybrid_lane": 4,
 OPS = {"preprocess": 0, "sort": 1, "raster_fwd": 2, "raster_bwd": 3, "preprocess_bwd": 4,
        "prepare_2d": 5, "all": 6}
 STATUS = {0: "GS_OK", 1: "GS_ERR_INVALID_ARGUMENT", 2: "GS_ERR_CAPACITY", 3: "GS_ERR_UNSUPPORTED",
-          4: "GS_ERR_HIP"}
+          4: "GS_ERR_HIP", 5: "GS_ERR_STATE"}
+STATUS_BITS = {1: "GS_STATUS_BAD_ID", 2: "GS_STATUS_FWD_SCHEDULE", 4: "GS_STATUS_BWD_SCHEDULE",
+               8: "GS_STATUS_STALE_RECORD"}
 
 
 class GsCamera(ctypes.Structure):
@@ -91,6 +93,10 @@ _SIGS = {
     "gs_preprocess_bwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                          c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p,
                                          c_p, c_p, c_p, c_p]),
+    "gs_raster_status": (ctypes.c_int, [ctypes.POINTER(GsConfig), c_i, c_i, c_i, c_p, c_sz,
+                                        ctypes.POINTER(ctypes.c_uint32), c_p]),
+    "gs_raster_debug_schedule": (ctypes.c_int, [ctypes.POINTER(GsConfig), c_i, c_i, c_i, c_p,
+                                                c_sz, c_p, c_p, c_p, c_p, c_p, c_p]),
     "gs_tile_workspace_size": (c_sz, [c_i, ctypes.c_int64, c_i, c_i]),
     "gs_tile_prepare": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                        c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
@@ -224,6 +230,22 @@ def gs_preprocess_bwd(cam: GsCamera, cfg: GsConfig, n, means3d, scales, quats, o
         _ptr(opacities), _ptr(sh), _ptr(dL_dmeans2d), _ptr(dL_dconics), _ptr(dL_drgb),
         _ptr(dL_dopacities2d), _ptr(dL_dmeans3d), _ptr(dL_dscales), _ptr(dL_dquats),
         _ptr(dL_dopacities), _ptr(dL_dsh), stream))
+
+
+def gs_raster_status(cfg: GsConfig, n, width, height, ws, ws_bytes, stream) -> int:
+    """The raster's device status word (waits for the stream); raises GsrError when non-zero."""
+    word = ctypes.c_uint32(0)
+    _check("gs_raster_status", lib().gs_raster_status(ctypes.byref(cfg), n, width, height,
+                                                      _ptr(ws), ws_bytes, ctypes.byref(word),
+                                                      stream))
+    return int(word.value)
+
+
+def gs_raster_debug_schedule(cfg: GsConfig, n, width, height, ws, ws_bytes, fwd_order, bwd_order,
+                             item_order, items, n_items, stream):
+    _check("gs_raster_debug_schedule", lib().gs_raster_debug_schedule(
+        ctypes.byref(cfg), n, width, height, _ptr(ws), ws_bytes, _ptr(fwd_order), _ptr(bwd_order),
+        _ptr(item_order), _ptr(items), _ptr(n_items), stream))
 
 
 def gs_tile_workspace_size(n, pair_capacity, width, height) -> int:

@@ -401,6 +401,45 @@ int gs_preprocess_bwd(const gs_camera* cam, const gs_config* cfg, int32_t n, con
                       "gs_preprocess_bwd");
 }
 
+int gs_raster_status(const gs_config* cfg, int32_t n, int32_t width, int32_t height,
+                     const void* ws, size_t ws_bytes, uint32_t* status, void* stream) {
+    GSR_TRY(check_dims(width, height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    GSR_NEED(status);
+    gsr::Views vs{1, 0};
+    GSR_TRY(check_ws_views(const_cast<void*>(ws), ws_bytes,
+                           gsr::raster_ws_bytes(n, width, height, false), views_of(cfg), vs));
+    uint32_t word = 0u;
+    const int rc = hip_status(gsr::raster_status(ws, n, width, height, &word, (hipStream_t)stream, vs),
+                              "gs_raster_status");
+    if (rc != GS_OK) return rc;
+    *status = word;
+    if (word == 0u) return ok();
+    return fail(GS_ERR_STATE, "raster status 0x%x:%s%s%s%s", word,
+                (word & GS_STATUS_BAD_ID) ? " sorted id out of range;" : "",
+                (word & GS_STATUS_FWD_SCHEDULE) ? " forward schedule entry out of range;" : "",
+                (word & GS_STATUS_BWD_SCHEDULE) ? " backward schedule entry out of range;" : "",
+                (word & GS_STATUS_STALE_RECORD) ? " staged record of other inputs;" : "");
+}
+
+int gs_raster_debug_schedule(const gs_config* cfg, int32_t n, int32_t width, int32_t height,
+                             const void* ws, size_t ws_bytes, int32_t* fwd_order,
+                             int32_t* bwd_order, int32_t* item_order, int32_t* items,
+                             int64_t* n_items, void* stream) {
+    GSR_TRY(check_dims(width, height));
+    GSR_TRY(check_cfg(cfg));
+    GSR_TRY(check_n(n));
+    gsr::Views vs{1, 0};
+    GSR_TRY(check_ws_views(const_cast<void*>(ws), ws_bytes,
+                           gsr::raster_ws_bytes(n, width, height, false), views_of(cfg), vs));
+    if ((item_order || items || n_items) && !gsr::raster_has_split(n, width, height))
+        return fail(GS_ERR_UNSUPPORTED, "this workspace holds no depth-split schedule");
+    return hip_status(gsr::copy_raster_schedule(ws, n, width, height, fwd_order, bwd_order,
+                                                item_order, items, n_items, (hipStream_t)stream, vs),
+                      "gs_raster_debug_schedule");
+}
+
 // ---- tile-based comparison rasterizer --------------------------------------------------------
 
 size_t gs_tile_workspace_size(int32_t n, int64_t pair_capacity, int32_t width, int32_t height) {

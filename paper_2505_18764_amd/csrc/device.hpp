@@ -114,6 +114,19 @@ __device__ __forceinline__ void wave_sum9(const float (&g)[9], float& a, float& 
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 
+// Compensated FP32 accumulation into a (hi, lo) pair of global words: the atomic add to hi
+// returns the value it added to, so the add's exact rounding error follows from Knuth's TwoSum
+// and goes to lo with a second atomic. hi + lo then equals the exact sum of all the values added,
+// up to the rounding of lo's own (much smaller) adds, in whatever order the adds arrive: the
+// sum no longer depends on the order in which workgroups reach the word.
+__device__ __forceinline__ void atomic_add_f32_comp(float* hi, float* lo, float v) {
+    const float old = unsafeAtomicAdd(hi, v);
+    const float s = old + v;                  // the value the atomic stored (IEEE RNE)
+    const float bv = s - old;
+    const float err = (old - (s - bv)) + (v - bv);
+    if (err != 0.f) unsafeAtomicAdd(lo, err);
+}
+
 // View-batched launches (grid y = view): p moved to this workgroup's view, where one view's part
 // of the array is `per_view` elements (view_at) or bytes (view_bytes). Null stays null.
 template <class T>

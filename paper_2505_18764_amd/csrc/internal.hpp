@@ -42,7 +42,10 @@ inline Views one_view() { return Views{1, 0}; }
 // ---- layout of the raster workspace -------------------------------------------------------
 constexpr int TILE = 32;              // pixels per side of the tile one workgroup owns
 constexpr int REC_BYTES = 48;         // one staged splat record
-constexpr int GRAD_STRIDE = 16;       // floats per splat in the gradient accumulation buffer
+// floats per splat in the gradient accumulation buffer: the nine sums [0, 9), the rounding errors
+// of the tile reduction's compensated adds to them [9, 18) (zero in the per-fragment modes), pad
+constexpr int GRAD_STRIDE = 20;
+constexpr int GRAD_LO = 9;
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -52,7 +55,8 @@ struct RasterWs {
     void* idrec;       // [n] 64-byte per-id records, the setup's staging in id order
     float* grad;       // [n * GRAD_STRIDE] (backward only)
     float* bgpart;     // [tiles][4] per-tile dL/dbackground partial sums (backward only)
-    unsigned long long* counters;  // [16] planner scratch
+    unsigned long long* counters;  // [16] planner scratch: [0] the work-item count, [1] the status word
+    uint32_t* status;  // device status word (gs_status_bits), cleared by every raster setup
     uint32_t* weights; // [tiles] splat count per tile
     int32_t* order;    // [tiles] tiles, heaviest first
     uint32_t* bwd_w;   // [tiles] the backward's walk length per tile (forward's estimate)
@@ -73,6 +77,13 @@ struct RasterWs {
 };
 size_t raster_ws_bytes(int n, int width, int height, bool bwd);
 RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd);
+// The status words of the views' slabs, OR-ed (synchronises the stream).
+hipError_t raster_status(const void* ws, int n, int width, int height, uint32_t* out,
+                         hipStream_t s, const Views& vs);
+bool raster_has_split(int n, int width, int height);
+hipError_t copy_raster_schedule(const void* ws, int n, int width, int height, int32_t* fwd_order,
+                                int32_t* bwd_order, int32_t* item_order, int32_t* items,
+                                int64_t* n_items, hipStream_t s, const Views& vs);
 
 size_t sort_ws_bytes(int n, int key_bytes);
 size_t compact_ws_bytes(int n);

@@ -21,6 +21,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "plan.hpp"
 
 namespace gsr {
 
@@ -76,12 +77,7 @@ constexpr size_t BITMAP_BUDGET = 1024u << 20;  // the bitmap is skipped above th
 // the segments in depth order. Only the at-rest, non-T-culled forward splits: T-culling and
 // per-fragment rounding of the stored state need the segments' inputs in sequence. Shorter
 // segments also keep each FP32 colour sum short.
-constexpr int NBUCKETS = 1024;
-constexpr int MAX_SEGMENTS = 32;
 constexpr int MAX_SPLIT_TILES = 4096;
-// Segment size: a third of the mean tile weight, so sum_t k_t <= 3 ntiles + ntiles.
-constexpr int SEG_DIV = 3;
-constexpr int ITEMS_PER_TILE = SEG_DIV + 1;
 
 // Exclusive scan of one value per thread over a workgroup of NBUCKETS (1024) threads: within each
 // wave by shuffles, then over the 16 wave totals. Returns the prefix; *total gets the sum.
@@ -108,24 +104,22 @@ __device__ uint32_t block_scan_1024(uint32_t v, uint32_t* total) {
     return before + incl - v;
 }
 
-// out[0 .. count) = indices ordered by decreasing bucket of w (one workgroup of 1024 threads);
-// out[count .. pad) = -1. Buckets split [0, wmax] evenly; the order within a bucket is arbitrary.
-__device__ void bucket_order(const uint32_t* __restrict__ w, int count, uint32_t wmax,
-                             int32_t* __restrict__ out, int pad, uint32_t* s_hist) {
-    const int tid = threadIdx.x;
-    for (int b = tid; b < NBUCKETS; b += blockDim.x) s_hist[b] = 0u;
-    __syncthreads();
-    const float scale = (float)NBUCKETS / ((float)wmax + 1.0f);
-    auto bucket = [&](uint32_t x) {
-        return NBUCKETS - 1 - min((int)((float)x * scale), NBUCKETS - 1);
-    };
-    for (int i = tid; i < count; i += blockDim.x) atomicAdd(&s_hist[bucket(w[i])], 1u);
-    __syncthreads();
-    const uint32_t first = block_scan_1024(s_hist[tid], nullptr);   // blockDim.x == NBUCKETS
-    s_hist[tid] = first;
-    __syncthreads();
-    for (int i = tid; i < count; i += blockDim.x) out[atomicAdd(&s_hist[bucket(w[i])], 1u)] = i;
-    for (int i = count + tid; i < pad; i += blockDim.x) out[i] = -1;
+// The schedulers' workgroup policy for bucket_order (plan.hpp): one workgroup of NBUCKETS threads.
+struct WgBlock {
+    template <class F>
+    __device__ void each(F&& f) { f((int)threadIdx.x, (int)blockDim.x); }
+    __device__ void sync() { __syncthreads(); }
+    __device__ uint32_t atomic_inc(uint32_t* p) { return atomicAdd(p, 1u); }
+    __device__ void exclusive_scan(uint32_t* h) {      // blockDim.x == NBUCKETS
+        const uint32_t first = block_scan_1024(h[threadIdx.x], nullptr);
+        h[threadIdx.x] = first;
+    }
+};
+
+// Error bits of the device status word (gs_raster_status): a kernel that meets a schedule entry
+// or a splat id outside its range records it here and skips that work instead of guessing.
+__device__ __forceinline__ void flag_status(uint32_t* status, uint32_t bit) {
+    if (status) atomicOr(status, bit);
 }
 
 // One workgroup: the tile order; with `split`, each tile's segment count k_t (its weight over
@@ -156,14 +150,13 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
     __syncthreads();
     const unsigned long long total = s_tot;
     const uint32_t wmax = s_max;
-    bucket_order(weights, ntiles, wmax, order, ntiles, s_hist);
+    WgBlock blk;
+    bucket_order(blk, weights, ntiles, wmax, order, ntiles, s_hist);
     if (!split) return;
     __syncthreads();
-    // k_t = ceil(w_t / cap), cap = ceil(mean weight / SEG_DIV): sum of k_t <= total / cap +
-    // ntiles <= ITEMS_PER_TILE ntiles
-    // cap <= max weight <= n < 2^31, so the per-tile division below is 32-bit
-    const uint32_t cap = (uint32_t)max(1ull, (total + (unsigned long long)SEG_DIV * ntiles - 1) /
-                                                 ((unsigned long long)SEG_DIV * ntiles));
+    // k_t segments per tile (segment_count), their exclusive scan the first item of each tile;
+    // the items number at most ITEMS_PER_TILE ntiles (segment_cap)
+    const uint32_t cap = segment_cap(total, ntiles);
     // exclusive scan of k_t over tiles: thread tid owns tiles [4 tid, 4 tid + 4) (ntiles <= 4096)
     int kk[4], loc = 0;
 #pragma unroll
@@ -171,8 +164,7 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_tiles(
         const int t = 4 * tid + r;
         int k = 0;
         if (t < ntiles) {
-            const uint32_t q = weights[t] / cap + (weights[t] % cap != 0u);
-            k = (int)min((uint32_t)MAX_SEGMENTS, max(1u, q));
+            k = segment_count(weights[t], cap);
             tile_k[t] = k;
         }
         kk[r] = k;
@@ -214,7 +206,7 @@ __global__ __launch_bounds__(64) void k_plan_cuts(
     __shared__ uint32_t cum[MAX_SEGMENTS + 1];
     __shared__ uint32_t tgt[MAX_SEGMENTS];           // cut j where the count first reaches tgt[j]
     if (lane <= MAX_SEGMENTS) { cut[lane] = lane ? ncol : 0; cum[lane] = lane ? w : 0u; }
-    if (lane < MAX_SEGMENTS) tgt[lane] = (uint32_t)(((unsigned long long)w * lane + k - 1) / k);
+    if (lane < MAX_SEGMENTS) tgt[lane] = cut_target(w, lane, k);
     __syncthreads();
     int found = 1;                                   // next cut to find
     uint32_t base = 0u;
@@ -272,7 +264,8 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_items(
     for (int i = threadIdx.x; i < count; i += blockDim.x) mx = max(mx, item_w[i]);
     atomicMax(&s_max, mx);
     __syncthreads();
-    bucket_order(item_w, count, s_max, item_order, cap, s_hist);
+    WgBlock blk;
+    bucket_order(blk, item_w, count, s_max, item_order, cap, s_hist);
 }
 
 // One workgroup: the backward's tile order, heaviest first by bwd_w (the forward's estimate of
@@ -290,7 +283,8 @@ __global__ __launch_bounds__(NBUCKETS) void k_plan_bwd(const uint32_t* __restric
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) mx = max(mx, bwd_w[t]);
     atomicMax(&s_max, mx);
     __syncthreads();
-    bucket_order(bwd_w, ntiles, s_max, order, ntiles, s_hist);
+    WgBlock blk;
+    bucket_order(blk, bwd_w, ntiles, s_max, order, ntiles, s_hist);
 }
 
 __device__ __forceinline__ bool rect_hit(uint2 r, uint32_t tx, uint32_t ty) {
@@ -338,14 +332,15 @@ __global__ __launch_bounds__(256) void k_raster_pack(
     int n, const float* __restrict__ means2d, const float* __restrict__ conics,
     const float* __restrict__ opac, const float* __restrict__ rgb, int W, int H, float amin,
     int saturate, IdRec* __restrict__ out, uint32_t* __restrict__ weights, int ntiles,
-    uint64_t vws) {
+    uint32_t* __restrict__ status, uint64_t vws) {
     means2d = view_at(means2d, 2ull * n);
     conics = view_at(conics, 3ull * n);
     rgb = view_at(rgb, 3ull * n);          // opacities are the views' shared [n]
     out = view_bytes(out, vws);
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0) {               // a new setup: weights and the status word start at 0
         weights = view_bytes(weights, vws);
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) weights[t] = 0u;
+        if (threadIdx.x == 0) *view_bytes(status, vws) = 0u;
     }
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n) return;
@@ -395,7 +390,8 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
     int n, const int32_t* __restrict__ sorted_ids, const int32_t* __restrict__ nvis_ptr,
     const IdRec* __restrict__ idrec, int tiles_x, int ntiles, Rec* __restrict__ rec,
     uint2* __restrict__ rect, uint32_t* __restrict__ weights,
-    uint32_t* __restrict__ bits, int wpr, uint16_t* __restrict__ colcnt, uint64_t vws) {
+    uint32_t* __restrict__ bits, int wpr, uint16_t* __restrict__ colcnt,
+    uint32_t* __restrict__ status, uint64_t vws) {
     // when ntiles <= MAX_LDS_TILES: [ntiles][COL_WORDS] chunk bits, then the tiles' 16-bit
     // counts two to a word (a count is at most SETUP_SPAN, so an add never carries across)
     extern __shared__ uint32_t s_dyn[];
@@ -424,6 +420,7 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
         const int p = p0 + j * SETUP_NT + threadIdx.x;
         const int id = p < nvis ? sorted_ids[p] : -1;
         ids[j] = (unsigned)id < (unsigned)n ? id : -1;
+        if (p < nvis && ids[j] < 0) flag_status(view_bytes(status, vws), GS_STATUS_BAD_ID);
     }
     IdRec q[SETUP_PER_THREAD];
 #pragma unroll
@@ -677,11 +674,11 @@ __device__ __forceinline__ void scan_round(Walk<RC>& w, const uint2* __restrict_
 }
 
 // Stages hits [b0, b0 + BATCH) of the round (in order across the four waves' lists).
-// The record's c.w is the splat id, which names its gradient slot: clamped to [0, n), so that a
-// setup that does not belong to these inputs gives wrong gradients but no access out of bounds.
+// The record's c.w is the splat id, which names its gradient slot: an id outside [0, n) (a setup
+// that does not belong to these inputs) is flagged in the status word and kept in bounds.
 template <int RC>
 __device__ __forceinline__ void stage(Walk<RC>& w, const Rec* __restrict__ rec, int n, int b0,
-                                      int total, int tid) {
+                                      int total, int tid, uint32_t* __restrict__ status) {
     const int e = b0 + tid;
     if (e < total) {
         int off = e, ws = 0;
@@ -695,7 +692,10 @@ __device__ __forceinline__ void stage(Walk<RC>& w, const Rec* __restrict__ rec, 
         const uint32_t v = w.seg[ws][off];
         const int pos = w.chunk[v / CHUNK_SPLATS] * CHUNK_SPLATS + (int)(v % CHUNK_SPLATS);
         Rec r = rec[pos];
-        r.c.w = min(r.c.w, (uint32_t)(n - 1));
+        if (r.c.w >= (uint32_t)n) {
+            flag_status(status, GS_STATUS_STALE_RECORD);
+            r.c.w = (uint32_t)(n - 1);
+        }
         w.rec[tid] = r;
     }
 }
@@ -728,8 +728,9 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     float amin, float amax, float tmin, float tsat, float bg0, float bg1, float bg2, int fb_fmt,
     void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T,
     int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats,
-    uint32_t* __restrict__ bwd_w, uint64_t vws) {
+    uint32_t* __restrict__ bwd_w, uint32_t* __restrict__ status, uint64_t vws) {
     __shared__ Walk<ROUND_CHUNKS> w;
+    status = view_bytes(status, vws);
     if constexpr (MULTI) {   // this view's walk state (its outputs are located at the write-back)
         nvis_ptr = view_at(nvis_ptr, 1);
         bwd_w = view_bytes(bwd_w, vws);
@@ -742,15 +743,28 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     }
     const int ncol = wpr / COL_WORDS;               // columns of SETUP_SPAN sorted positions
     int tile, c_begin = 0, c_end = ncol, slot = -1;
+    // A schedule entry outside its range (a schedule not built for this launch) is recorded in the
+    // status word and its work is skipped: each tile must be composited exactly once.
     if (items) {
         const int it = item_order[blockIdx.x];
-        if (it < 0 || it >= ITEMS_PER_TILE * ntiles) return;      // past the item count
+        if (it < 0) return;                                        // past the item count
+        if (it >= ITEMS_PER_TILE * ntiles) {
+            if (threadIdx.x == 0) flag_status(status, GS_STATUS_FWD_SCHEDULE);
+            return;
+        }
         const int4 v = items[it];
         tile = v.x; c_begin = v.y; c_end = v.z; slot = v.w;
-        if ((unsigned)tile >= (unsigned)ntiles || slot >= ITEMS_PER_TILE * ntiles) return;
+        if ((unsigned)tile >= (unsigned)ntiles || slot >= ITEMS_PER_TILE * ntiles ||
+            c_begin < 0 || c_end < c_begin) {
+            if (threadIdx.x == 0) flag_status(status, GS_STATUS_FWD_SCHEDULE);
+            return;
+        }
     } else {
         tile = order[blockIdx.x];
-        if ((unsigned)tile >= (unsigned)ntiles) tile = (int)blockIdx.x;   // a schedule not built for this grid
+        if ((unsigned)tile >= (unsigned)ntiles) {
+            if (threadIdx.x == 0) flag_status(status, GS_STATUS_FWD_SCHEDULE);
+            return;
+        }
     }
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
@@ -804,7 +818,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
         if (INSTR) { nq += total; nchk += w.nchunk; nbat += (total + BATCH - 1) / BATCH; }
         bool stop = false;
         for (int b0 = 0; b0 < total; b0 += BATCH) {
-            stage(w, rec, n, b0, total, tid);
+            stage(w, rec, n, b0, total, tid, status);
             __syncthreads();
             const int m = min(BATCH, total - b0);
             if (!TCULL || alive) {
@@ -1048,7 +1062,9 @@ __device__ __forceinline__ void reduce_commit(float (&g)[9], bool live, float* _
 }
 
 // GS_REDUCE_TILE: adds the staged batch's LDS accumulator (9 sums per entry) to the splats'
-// gradient slots, one set of global atomics per splat and tile, and clears it. Thread t takes
+// gradient slots, one set of compensated global atomics per splat and tile (a splat's slot
+// collects one add per tile it covers; compensation keeps that sum independent of the order in
+// which the tiles arrive, FP32 throughout), and clears it. Thread t takes
 // values t, t + NT, ..., so consecutive lanes add consecutive values of a slot and one wave's
 // atomics touch about 7 slots' cache lines instead of 64. Reads other entries' records: the caller
 // waits at a barrier before restaging them. Called before each restage and once after the walk.
@@ -1070,7 +1086,8 @@ __device__ __forceinline__ void flush_tile_grad(float* __restrict__ tg, const Wa
             const float v = tg[q];
             if (v != 0.f) {
                 const int e = q / 9;
-                atomic_add_f32(grad + (size_t)w.rec[e].c.w * GRAD_STRIDE + (q - 9 * e), v);
+                float* hi = grad + (size_t)w.rec[e].c.w * GRAD_STRIDE + (q - 9 * e);
+                atomic_add_f32_comp(hi, hi + GRAD_LO, v);
             }
         }
         tg[q] = 0.f;
@@ -1087,8 +1104,10 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     float amin, float amax, float tmin, int fb_fmt, const void* __restrict__ fb,
     const float* __restrict__ dL_dimg, const float* __restrict__ dL_dT,
     int mode, int X, float* __restrict__ grad, float* __restrict__ bgpart,
-    int32_t* __restrict__ out_live, unsigned long long* __restrict__ stats, uint64_t vws) {
+    int32_t* __restrict__ out_live, unsigned long long* __restrict__ stats,
+    uint32_t* __restrict__ status, uint64_t vws) {
     __shared__ Walk<BWD_ROUND_CHUNKS> w;
+    status = view_bytes(status, vws);
     __shared__ float tg[BATCH * 9];     // GS_REDUCE_TILE: per staged splat, the tile's gradient
     if constexpr (MULTI) {
         const uint64_t PV = (uint64_t)W * H;
@@ -1104,8 +1123,11 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
         dL_dT = view_at(dL_dT, PV);
         out_live = view_at(out_live, PV);
     }
-    int tile = order[blockIdx.x];
-    if ((unsigned)tile >= gridDim.x) tile = (int)blockIdx.x;   // a schedule not built for this grid
+    const int tile = order[blockIdx.x];
+    if ((unsigned)tile >= gridDim.x) {     // a schedule not built for this grid: recorded, skipped
+        if (threadIdx.x == 0) flag_status(status, GS_STATUS_BWD_SCHEDULE);
+        return;
+    }
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const uint32_t ttx = (uint32_t)(tile % tiles_x), tty = (uint32_t)(tile / tiles_x);
@@ -1176,7 +1198,7 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                 pend = 0;
                 __syncthreads();                  // the flush read other threads' records
             }
-            stage(w, rec, n, b0, total, tid);
+            stage(w, rec, n, b0, total, tid, status);
             __syncthreads();
             const int m = min(BATCH, total - b0);
             pend = m;
@@ -1243,7 +1265,11 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                             Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
                             Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
                             Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
-                            T[s] = Ti - wt;                                   // Eq. 5
+                            // Eq. 5, with the forward's arithmetic: per-fragment FP16 state
+                            // is T (1 - alpha) as one FMA rounded once to half, as the forward's
+                            // half-precision blend stores it; the other formats round T - T alpha
+                            if constexpr (RFMT == FB_F16) T[s] = fmaf(-Ti, al, Ti);
+                            else T[s] = Ti - wt;
                             if constexpr (RFMT >= 0) {
                                 Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
                                 Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
@@ -1403,12 +1429,18 @@ __global__ __launch_bounds__(256) void k_grad_finalize(
     g_rgb = view_at(g_rgb, 3ull * n);
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n) return;
-    float v[9];
+    // each sum is hi + lo (lo: the compensated adds' rounding errors; zero in the per-fragment
+    // reduction modes), rounded once
+    float raw[20];
     const float4* gp = reinterpret_cast<const float4*>(grad + (size_t)id * GRAD_STRIDE);
-    const float4 u0 = gp[0], u1 = gp[1];
-    const float u2 = grad[(size_t)id * GRAD_STRIDE + 8];
-    v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
-    v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w; v[8] = u2;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const float4 u = gp[k];
+        raw[4 * k] = u.x; raw[4 * k + 1] = u.y; raw[4 * k + 2] = u.z; raw[4 * k + 3] = u.w;
+    }
+    float v[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) v[j] = raw[j] + raw[GRAD_LO + j];
     if (saturate)
         for (int ch = 0; ch < 3; ++ch)
             if (rgb[3 * (size_t)id + ch] > 1.f) v[6 + ch] = 0.f;
@@ -1452,9 +1484,11 @@ size_t raster_ws_bytes(int n, int width, int height, bool bwd) {
         b += align_up(nt * (wpr / COL_WORDS) * 2) + align_up(ITEMS_PER_TILE * nt * 16) +
              2 * align_up(ITEMS_PER_TILE * nt * 4) + 2 * align_up(nt * 4) +
              align_up(ITEMS_PER_TILE * nt * TILE * TILE * 16);
-    // the setup's per-id staging and the backward's gradient slots share one region (64 B per
-    // splat): the staging is dead once the setup has run, before the gradients are cleared
-    static_assert(GRAD_STRIDE * 4 == sizeof(IdRec), "shared region");
+    // the setup's per-id staging (64 B per splat) and the backward's gradient slots (80 B per
+    // splat) share one region: the staging is dead once the setup has run, before the gradients
+    // are cleared
+    static_assert(GRAD_STRIDE * 4 >= sizeof(IdRec) && GRAD_STRIDE % 4 == 0, "shared region");
+    static_assert(GRAD_LO + 9 <= GRAD_STRIDE, "slot layout");
     b += align_up((size_t)n * GRAD_STRIDE * 4);
     if (bwd) b += align_up(nt * 16);
     return b;
@@ -1467,6 +1501,7 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     r.rec = p;      p += align_up((size_t)n * REC_BYTES);
     r.rect = p;     p += align_up((size_t)n * 8);
     r.counters = (unsigned long long*)p; p += align_up(16 * 8);
+    r.status = (uint32_t*)(r.counters + 1);
     r.weights = (uint32_t*)p; p += align_up(nt * 4);
     r.order = (int32_t*)p;    p += align_up(nt * 4);
     r.bwd_w = (uint32_t*)p;   p += align_up(nt * 4);
@@ -1507,18 +1542,19 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
     const int V = vs.count;
     if (n == 0) {
         hipError_t e = launch_fill_u32(r.weights, (size_t)ntiles, 0u, s, V, vs.ws);
+        if (e == hipSuccess) e = launch_fill_u32(r.status, 1, 0u, s, V, vs.ws);
         if (e != hipSuccess) return e;
     } else {
         const int sat = (cfg.fb_format == FB_UNORM16 || cfg.fb_format == FB_UNORM8) ? 1 : 0;
         hipLaunchKernelGGL(k_raster_pack, dim3((n + 255) / 256, V), dim3(256), 0, s, n, means2d,
                            conics, opac, rgb, width, height, cfg.alpha_min, sat, (IdRec*)r.idrec,
-                           r.weights, ntiles, vs.ws);
+                           r.weights, ntiles, r.status, vs.ws);
         const size_t lds =
             ntiles <= MAX_LDS_TILES ? ((size_t)ntiles * COL_WORDS + (ntiles + 1) / 2) * 4 : 0;
         hipLaunchKernelGGL(k_raster_setup, dim3((n + SETUP_SPAN - 1) / SETUP_SPAN, V),
                            dim3(SETUP_NT), lds, s, n, sorted_ids, n_visible,
                            (const IdRec*)r.idrec, tiles_x, ntiles, (Rec*)r.rec, (uint2*)r.rect,
-                           r.weights, r.bits, r.wpr, r.colcnt, vs.ws);
+                           r.weights, r.bits, r.wpr, r.colcnt, r.status, vs.ws);
     }
     hipLaunchKernelGGL(k_plan_tiles, dim3(1, V), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
                        r.split, r.tile_k, r.tile_first, r.counters, r.bwd_w, vs.ws);
@@ -1536,6 +1572,50 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
 
 static bool saturating(int fmt) { return fmt == FB_UNORM16 || fmt == FB_UNORM8; }
 
+hipError_t raster_status(const void* ws, int n, int width, int height, uint32_t* out,
+                         hipStream_t s, const Views& vs) {
+    const RasterWs r = carve_raster_ws(const_cast<void*>(ws), n, width, height, false);
+    uint32_t acc = 0u;
+    for (int v = 0; v < vs.count; ++v) {
+        uint32_t word = 0u;
+        const char* src = reinterpret_cast<const char*>(r.status) + (size_t)v * vs.ws;
+        hipError_t e = hipMemcpyAsync(&word, src, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        acc |= word;
+    }
+    *out = acc;
+    return hipSuccess;
+}
+
+bool raster_has_split(int n, int width, int height) { return split_ok(n, width, height); }
+
+hipError_t copy_raster_schedule(const void* ws, int n, int width, int height, int32_t* fwd_order,
+                                int32_t* bwd_order, int32_t* item_order, int32_t* items,
+                                int64_t* n_items, hipStream_t s, const Views& vs) {
+    const RasterWs r = carve_raster_ws(const_cast<void*>(ws), n, width, height, false);
+    const size_t nt = (size_t)tiles_of(width, height);
+    for (int v = 0; v < vs.count; ++v) {
+        const size_t off = (size_t)v * vs.ws;
+        auto at = [&](const void* p) { return reinterpret_cast<const char*>(p) + off; };
+        hipError_t e = hipSuccess;
+        if (fwd_order)
+            e = hipMemcpyAsync(fwd_order + v * nt, at(r.order), nt * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && bwd_order)
+            e = hipMemcpyAsync(bwd_order + v * nt, at(r.bwd_order), nt * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && item_order)
+            e = hipMemcpyAsync(item_order + v * ITEMS_PER_TILE * nt, at(r.item_order),
+                               ITEMS_PER_TILE * nt * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && items)
+            e = hipMemcpyAsync(items + v * 4 * ITEMS_PER_TILE * nt, at(r.items),
+                               ITEMS_PER_TILE * nt * 16, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && n_items)
+            e = hipMemcpyAsync(n_items + v, at(r.counters), 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int n,
                                const int32_t* sorted_ids, const int32_t* n_visible,
                                const float* means2d, const float* conics, const float* opac,
@@ -1548,7 +1628,8 @@ hipError_t launch_raster_setup(const gs_config& cfg, int width, int height, int 
 using FwdKernel = void (*)(int, const int32_t*, const Rec*, const uint2*, const int32_t*,
                           const uint32_t*, int, int, int, int, int, const int4*, const int32_t*,
                           float4*, float, float, float, float, float, float, float, int, void*,
-                          float*, float*, int32_t*, unsigned long long*, uint32_t*, uint64_t);
+                          float*, float*, int32_t*, unsigned long long*, uint32_t*, uint32_t*,
+                          uint64_t);
 
 template <bool TC, bool IN, bool MU>
 static FwdKernel fwd_by_fmt(int rfmt) {
@@ -1599,7 +1680,7 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                        cfg.background[1], cfg.background[2], cfg.fb_format, fb, out_rgb, out_T,
                        out_cov,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr,
-                       r.bwd_w,
+                       r.bwd_w, r.status,
                        vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !split) return e;
@@ -1637,7 +1718,7 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_live;
     void (*k)(int, const int32_t*, const Rec*, const uint2*, const int32_t*, const uint32_t*, int,
               int, int, int, float, float, float, int, const void*, const float*, const float*, int,
-              int, float*, float*, int32_t*, unsigned long long*, uint64_t) = nullptr;
+              int, float*, float*, int32_t*, unsigned long long*, uint32_t*, uint64_t) = nullptr;
 #define GSR_BWD_PICK(IN, MU, TM)                                             \
     switch (rfmt) {                                                          \
     case FB_F32: k = k_raster_bwd<FB_F32, IN, MU, TM>; break;                \
@@ -1664,7 +1745,7 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                        dL_dT, cfg.reduce_mode, cfg.reduce_threshold, r.grad,
                        dL_dbg ? r.bgpart : nullptr, out_live,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr,
-                       vs.ws);
+                       r.status, vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n == 0) {                        // no gradients to finalise: the background alone

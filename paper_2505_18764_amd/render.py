@@ -106,6 +106,7 @@ class Workspace:
     def __init__(self, device="cuda"):
         self.device = torch.device(device)
         self.buf = None
+        self.setup_owner = None     # who built the raster setup the buffer holds (see own_setup)
 
     def get(self, nbytes: int, keep: bool = False):
         """A buffer of at least nbytes; with keep, a grown buffer starts with the old contents."""
@@ -114,8 +115,19 @@ class Workspace:
             new = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             if keep and self.buf is not None:
                 new[: self.buf.numel()].copy_(self.buf)
+            else:
+                self.setup_owner = None
             self.buf = new
         return self.buf
+
+    def own_setup(self):
+        """A token for the raster setup about to be built in this buffer; holds_setup(token)
+        stays true until another setup is built here or the buffer is replaced."""
+        self.setup_owner = object()
+        return self.setup_owner
+
+    def holds_setup(self, token) -> bool:
+        return token is not None and self.setup_owner is token
 
     @property
     def nbytes(self) -> int:
@@ -126,8 +138,13 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def _ws_args(ws: Workspace, need: int):
+def _ws_args(ws: Workspace, need: int, keep_setup: bool = False):
+    """The workspace buffer for a call that needs `need` bytes. Every call writes scratch over the
+    buffer's front, where a raster setup lives, so the setup's ownership ends here unless the
+    call reads that setup (keep_setup)."""
     b = ws.get(need)
+    if not keep_setup:
+        ws.setup_owner = None
     return b, b.numel()
 
 
@@ -241,13 +258,16 @@ FB_BYTES = {"f32": 16, "f16": 8, "unorm16": 8, "bf16": 8, "unorm8": 4}
 def raster_setup(p: Projected, cfg: RasterConfig, ws: Workspace):
     """gs_raster_setup: builds the records, bitmap and tile schedule that a following
     raster_forward / raster_backward with reuse_setup=True on the same workspace share. The
-    workspace is sized for the backward here, so those calls never regrow (and lose) it."""
+    workspace is sized for the backward here, so those calls never regrow (and lose) it.
+    Returns the workspace's ownership token of this setup (Workspace.holds_setup)."""
     dev = p.means2d.device
     W, H, n = p.width, p.height, p.n
     cc, cm = cfg.c(p.n_views), image_camera(W, H)
     b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc))
+    token = ws.own_setup()
     L.gs_raster_setup(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, b, nb,
                       _stream(dev))
+    return token
 
 
 def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, image=None, T=None,
@@ -271,7 +291,7 @@ def raster_forward(p: Projected, cfg: RasterConfig, ws: Workspace, fb=None, imag
     cov = torch.empty(*lead, H, W, dtype=torch.int32, device=dev) if coverage else None
     if stats is not None:
         cc.flags |= 1
-    b, nb = _ws_args(ws, L.gs_workspace_size("raster_fwd", n, W, H, cc))
+    b, nb = _ws_args(ws, L.gs_workspace_size("raster_fwd", n, W, H, cc), keep_setup=reuse_setup)
     L.gs_raster_fwd(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, fb,
                     image, T, cov, stats, b, nb, _stream(dev))
     return dict(fb=fb, image=image, T=T, coverage=cov)
@@ -299,12 +319,41 @@ def raster_backward(p: Projected, fb, dL_dimage, cfg: RasterConfig, ws: Workspac
     lv = torch.empty(*lead, H, W, dtype=torch.int32, device=dev) if live else None
     if stats is not None:
         cc.flags |= 1
-    b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc))
+    b, nb = _ws_args(ws, L.gs_workspace_size("raster_bwd", n, W, H, cc), keep_setup=reuse_setup)
     L.gs_raster_bwd(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, p.rgb, fb,
                     _c32(dL_dimage), out["means2d"], out["conics"], out["opacities"], out["rgb"],
                     None if dL_dT is None else _c32(dL_dT), out["background"], lv, stats, b, nb,
                     _stream(dev))
     out["live"] = lv
+    return out
+
+
+def raster_status(p: Projected, cfg: RasterConfig, ws: Workspace) -> int:
+    """gs_raster_status: waits for the stream and raises GsrError (GS_ERR_STATE) if a raster
+    kernel met a splat id or a schedule entry outside its range since the last raster setup on
+    this workspace; returns the (zero) status word."""
+    cc = cfg.c(p.n_views)
+    b = ws.buf
+    return L.gs_raster_status(cc, p.n, p.width, p.height, b, 0 if b is None else b.numel(),
+                              _stream(p.means2d.device))
+
+
+def raster_schedule(p: Projected, cfg: RasterConfig, ws: Workspace, items: bool = False) -> dict:
+    """gs_raster_debug_schedule: the tile orders of the forward and the backward ([T] each, or
+    [V, T]) and, with items, the depth split's work items ([4T] order, [4T, 4] items, item count)."""
+    dev = p.means2d.device
+    T = ((p.width + 31) // 32) * ((p.height + 31) // 32)
+    lead = p.lead()
+    out = dict(fwd_order=torch.empty(*lead, T, dtype=torch.int32, device=dev),
+               bwd_order=torch.empty(*lead, T, dtype=torch.int32, device=dev))
+    if items:
+        out.update(item_order=torch.empty(*lead, 4 * T, dtype=torch.int32, device=dev),
+                   items=torch.empty(*lead, 4 * T, 4, dtype=torch.int32, device=dev),
+                   n_items=torch.empty(*lead, 1, dtype=torch.int64, device=dev))
+    b = ws.buf
+    L.gs_raster_debug_schedule(cfg.c(p.n_views), p.n, p.width, p.height, b, b.numel(),
+                               out["fwd_order"], out["bwd_order"], out.get("item_order"),
+                               out.get("items"), out.get("n_items"), _stream(dev))
     return out
 
 
@@ -341,7 +390,8 @@ class GaussianRasterizeFn(torch.autograd.Function):
     def forward(ctx, means3d, scales, quats, opacities, sh, cam, cfg, ws):
         ctx.set_materialize_grads(False)
         p = project(means3d, scales, quats, opacities, sh, cam, cfg, ws)
-        out = raster_forward(p, cfg, ws)
+        ctx.setup = raster_setup(p, cfg, ws)
+        out = raster_forward(p, cfg, ws, reuse_setup=True)
         ctx.cam, ctx.cfg, ctx.ws, ctx.proj = cam, cfg, ws, p
         ctx.save_for_backward(means3d, scales, quats, opacities, sh, out["fb"])
         return out["image"], out["T"]
@@ -352,7 +402,8 @@ class GaussianRasterizeFn(torch.autograd.Function):
         if d_image is None:
             d_image = torch.zeros(*ctx.proj.lead(), 3, ctx.proj.height, ctx.proj.width,
                                   device=fb.device)
-        g2 = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws, dL_dT=d_T)
+        g2 = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws, dL_dT=d_T,
+                             reuse_setup=ctx.ws.holds_setup(ctx.setup))
         g3 = project_backward(means3d, scales, quats, opacities, sh, ctx.cam, ctx.cfg, g2)
         return g3["means3d"], g3["scales"], g3["quats"], g3["opacities"], g3["sh"], None, None, None
 
@@ -364,7 +415,8 @@ class Raster2DFn(torch.autograd.Function):
     def forward(ctx, means2d, conics, opacities, rgb, depth, width, height, cfg, ws):
         ctx.set_materialize_grads(False)
         p = prepare_2d(means2d, conics, opacities, rgb, depth, width, height, cfg, ws)
-        out = raster_forward(p, cfg, ws)
+        ctx.setup = raster_setup(p, cfg, ws)
+        out = raster_forward(p, cfg, ws, reuse_setup=True)
         ctx.cfg, ctx.ws, ctx.proj = cfg, ws, p
         ctx.save_for_backward(out["fb"])
         return out["image"], out["T"]
@@ -374,7 +426,8 @@ class Raster2DFn(torch.autograd.Function):
         (fb,) = ctx.saved_tensors
         if d_image is None:
             d_image = torch.zeros(3, ctx.proj.height, ctx.proj.width, device=fb.device)
-        g = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws, dL_dT=d_T)
+        g = raster_backward(ctx.proj, fb, d_image.contiguous(), ctx.cfg, ctx.ws, dL_dT=d_T,
+                            reuse_setup=ctx.ws.holds_setup(ctx.setup))
         return g["means2d"], g["conics"], g["opacities"], g["rgb"], None, None, None, None, None
 
 
@@ -400,12 +453,13 @@ def tile_forward(p: Projected, cfg: RasterConfig, ws: Workspace, out=None):
     cc, cm = cfg.c(), image_camera(W, H)
     st = _stream(dev)
     n_pairs = torch.zeros(1, dtype=torch.int32, device=dev)
-    b = ws.get(L.gs_tile_workspace_size(n, 0, W, H))
+    b, _ = _ws_args(ws, L.gs_tile_workspace_size(n, 0, W, H))
     L.gs_tile_prepare(cm, cc, n, p.ids, p.n_visible, p.means2d, p.conics, p.opacities, n_pairs, b,
                       b.numel(), st)
     npairs = int(n_pairs.item())
     cap = max(npairs, 1)
     b = ws.get(L.gs_tile_workspace_size(n, cap, W, H), keep=True)
+    ws.setup_owner = None
     if out is None:
         out = dict(image=torch.empty(3, H, W, device=dev), T=torch.empty(H, W, device=dev),
                    n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev))
@@ -426,6 +480,7 @@ def tile_backward(p: Projected, fwd: dict, dL_dimage, cfg: RasterConfig, ws: Wor
     if "background" not in out:
         out["background"] = torch.empty(3, device=dev)
     b = ws.get(L.gs_tile_workspace_size(n, fwd["capacity"], W, H), keep=True)
+    ws.setup_owner = None
     L.gs_tile_raster_bwd(cm, cc, n, p.means2d, p.conics, p.opacities, p.rgb, _c32(dL_dimage),
                          fwd["T"], fwd["n_contrib"], fwd["capacity"], out["means2d"],
                          out["conics"], out["opacities"], out["rgb"], b, b.numel(), _stream(dev))

@@ -156,6 +156,19 @@ def test_invalid_arguments_rejected_on_host():
     cz.znear = 0.0
     assert L.lib().gs_preprocess_bwd(ctypes.byref(cz), ctypes.byref(cfg), 0, *([None] * 14),
                                      None) == 1
+    # the status query and the schedule copy validate before touching the device
+    word = ctypes.c_uint32(7)
+    assert L.lib().gs_raster_status(ctypes.byref(cfg), 10, 64, 48, ws, 16, ctypes.byref(word),
+                                    None) == 2                    # workspace too small
+    assert L.lib().gs_raster_status(ctypes.byref(cfg), 10, 64, 48, ws, 1 << 30, None, None) == 1
+    assert L.lib().gs_raster_status(ctypes.byref(cfg), 10, 0, 48, ws, 1 << 30, ctypes.byref(word),
+                                    None) == 1
+    assert word.value == 7                                        # untouched on failure
+    assert L.lib().gs_raster_debug_schedule(ctypes.byref(cfg), 10, 64, 48, None, 0, f, f, None,
+                                            None, None, None) == 1
+    big = 100 * 32                                                # > 4096 tiles: no depth split
+    assert L.lib().gs_raster_debug_schedule(ctypes.byref(cfg), 10, big, big, ws, 1 << 40, None,
+                                            None, f, None, None, None) == 3
 
 
 def test_view_batches_checked_on_host():

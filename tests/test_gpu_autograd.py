@@ -56,7 +56,7 @@ def test_autograd_gradients_match_oracle_chain():
                logits=p.logits.grad, sh=p.sh.grad)
     errs = {k: rel_l2(got[k].cpu().numpy(), exp_[k]) for k in exp_}
     print(errs)
-    assert max(errs.values()) <= 1e-3, errs
+    assert max(errs.values()) <= 1e-4, errs           # the FP32 gradient contract, per group
     assert T.requires_grad          # a loss on T reaches the splats through dL/dT_final
 
 
@@ -119,7 +119,7 @@ def test_finite_differences_on_64_parameters():
     err = rel_l2(an, fd)
     print("FD samples", len(fd), "rel-L2", err)
     assert len(fd) == 64
-    assert err <= 1e-3, err
+    assert err <= 1e-4, err                           # GPU vs FD on the FP64 oracle (R21)
 
 
 @pytest.mark.parametrize("views_per_step", [1, 4])

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import group_errors, grads9, rel_l2, t
+from tests.helpers import certain_grad, group_errors, grads9, rel_l2, t
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -86,7 +86,7 @@ def test_projection_backward_parity():
         b = ref[k][keep]
         e = rel_l2(a, b)
         print(k, e)
-        assert e < 2e-4, (k, e)
+        assert e < 1e-4, (k, e)
     assert (out["means3d"].cpu().numpy()[~pre["visible"] & ~pre["ambiguous"]] == 0).all()
 
 
@@ -138,7 +138,10 @@ def test_end_to_end_chain():
     (FP64 projection, FP64 raster, complex-step projection backward)."""
     sc, cam = _scene(20_000, 9, 192, 144)
     W, H = cam.width, cam.height
-    G = synth.image_grad(W, H, 19)
+    ocfg = oracle.OracleConfig(beta=1e-5, beta_abs=2e-3, tau=1e-3)
+    # dL/dC zero at the pixels with a borderline decision (R19), where FP32 inputs may decide
+    # either way
+    G = certain_grad(synth.image_grad(W, H, 19), oracle.render_scene(sc, cam, cfg=ocfg)["amb"])
     cfg = R.RasterConfig()
     ws = R.Workspace()
     args = [t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh)]
@@ -147,17 +150,16 @@ def test_end_to_end_chain():
     b = R.raster_backward(p, f["fb"], t(G), cfg, ws)
     g3 = R.project_backward(*args, cam, cfg, b)
     torch.cuda.synchronize()
-    ocfg = oracle.OracleConfig(beta=1e-5, beta_abs=2e-3, tau=1e-3)
     ref = oracle.render_scene(sc, cam, dL_dimg=G, cfg=ocfg)
     ok = ref["amb"] == 0
     img = f["image"].cpu().numpy()
     d = np.abs(img - ref["img"])[:, ok].max()
     print("end-to-end image max-abs (unflagged)", d, "flagged px", (~ok).mean())
-    assert d <= 1e-4
+    assert d <= 1e-5
     og = ref["grad"]
     ov = oracle.preprocess_vjp(sc, cam, og[:, 0:2], og[:, 2:5], og[:, 6:9], og[:, 5])
     errs = {k: rel_l2(g3[k].cpu().numpy(), ov[k]) for k in ov}
     allg = rel_l2(np.concatenate([g3[k].cpu().numpy().reshape(-1) for k in ov]),
                   np.concatenate([ov[k].reshape(-1) for k in ov]))
     print("end-to-end 3D gradient rel-L2", errs, "all", allg)
-    assert allg <= 1e-3
+    assert max(max(errs.values()), allg) <= 1e-4, (errs, allg)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import group_errors, grads9, rel_l2, t
+from tests.helpers import certain_grad, check_schedule, group_errors, grads9, rel_l2, t
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -27,6 +27,8 @@ def _run(s, W, H, G, cfg, stats=False):
     p = R.prepare_2d(t(s.means2d), t(s.conics), t(s.opacities), t(s.rgb), t(s.depth), W, H, cfg, ws)
     f = R.raster_forward(p, cfg, ws, coverage=True, stats=st)
     b = R.raster_backward(p, f["fb"], t(G), cfg, ws, live=True, stats=st)
+    assert R.raster_status(p, cfg, ws) == 0       # no id or schedule entry out of range
+    check_schedule(R, p, cfg, ws)
     torch.cuda.synchronize()
     out = dict(img=f["image"].cpu().numpy(), T=f["T"].cpu().numpy(), cov=f["coverage"].cpu().numpy(),
                live=b["live"].cpu().numpy(), grad=grads9(b), nvis=int(p.n_visible.item()),
@@ -61,8 +63,10 @@ def _check(out, ref, img_tol=1e-5, grad_tol=1e-4, counts=True):
         bad = ~ok
         assert (out["cov"][bad] >= ref["cov"][bad] - ref["amb"][bad]).all()
         assert (out["cov"][bad] <= ref["cov"][bad] + ref["amb"][bad]).all()
+    # R16: every parameter group is held to the bar, not only the all-parameter norm, which the
+    # conic group dominates
     e = group_errors(out["grad"], ref["grad"])
-    assert e["all"] <= grad_tol, e
+    assert max(e.values()) <= grad_tol, e
     return e
 
 
@@ -185,6 +189,9 @@ def test_depth_split_forward():
     R.raster_setup(p, cfg, ws)
     f = R.raster_forward(p, cfg, ws, reuse_setup=True)               # split + merge
     bw = R.raster_backward(p, f["fb"], t(G), cfg, ws, live=True, reuse_setup=True)
+    sch = check_schedule(R, p, cfg, ws, items=True)
+    assert int(sch["n_items"].item()) > (W // 32) * (H // 32)          # some tiles were split
+    assert R.raster_status(p, cfg, ws) == 0
     f2 = R.raster_forward(p, cfg, ws, coverage=True, reuse_setup=True)   # one pass per tile
     torch.cuda.synchronize()
     img, T = f["image"].cpu().numpy(), f["T"].cpu().numpy()
@@ -238,13 +245,19 @@ def test_formats_against_emulating_oracle(fmt, rnd):
                                                   beta=1e-6, beta_abs=4e-6, tau=tau))
     ok = emu["amb"] == 0
     d = np.abs(out["img"] - emu["img"])[:, ok]
+    e_emu = group_errors(out["grad"], emu["grad"])
+    print(f"{fmt}/{rnd} vs emulation: image max {d.max() / ulp:.2f} ulp, median "
+          f"{np.median(d) / ulp:.3f} ulp, mean {d.mean() / ulp:.3f} ulp; grad {e_emu}")
+    # The emulation is pinned to hand-rounded closed forms (test_oracle_raster.py): it rounds at
+    # exactly the stores the GPU rounds at. What remains is FP32 against FP64 arithmetic before
+    # each rounding, which flips a rounding decision now and then, one format step on one value
+    # (measured: image within 4 steps at the worst pixel, gradients within 4e-4 relative).
     if rnd == "at_rest":
         assert d.max() <= 1.01 * ulp                     # at most one rounding step apart
         assert (d > 0.5 * ulp).mean() < 0.02          # differing rounding decisions are rare
-        assert rel_l2(out["grad"], emu["grad"]) <= 2e-3
     else:
-        assert np.median(d) <= ulp and d.mean() <= 2 * ulp
-        assert rel_l2(out["grad"], emu["grad"]) <= 0.1
+        assert d.max() <= 8 * ulp and d.mean() <= 0.1 * ulp
+    assert e_emu["all"] <= 2e-3, e_emu
     plain = _oracle(s, W, H, G, oracle.OracleConfig(**BAND))
     err_img = np.abs(out["img"] - plain["img"])[:, plain["amb"] == 0].max()
     err_grad = rel_l2(out["grad"], plain["grad"])
@@ -374,15 +387,17 @@ def test_image_wide_splats_in_front(mode):
     small = synth.splats2d(n=3000, width=W, height=H, seed=32)
     s = types.SimpleNamespace(**{k: np.concatenate([getattr(big, k), getattr(small, k)])
                                  for k in ("means2d", "conics", "opacities", "rgb", "depth")})
-    G = synth.image_grad(W, H, 33)
+    # The 400 image-wide splats' boundaries cross the image, so some pixels hold borderline alpha
+    # decisions (R19); the huge splats' gradients are sums over the whole image with cancelling
+    # dL/dC, and the flagged 0.1 % of pixels carry about 3 % of them, so one flip there moves a
+    # gradient by ~1e-4. Gradients are compared with dL/dC zero at the flagged pixels (the image
+    # check skips them too); unmasked, both reductions measured 2.2e-4 over all parameters.
+    ocfg = oracle.OracleConfig(**BAND)
+    G = certain_grad(synth.image_grad(W, H, 33), _oracle(s, W, H, None, ocfg)["amb"])
     cfg = R.RasterConfig(reduce_mode=mode)
     out = _run(s, W, H, G, cfg)
-    ref = _oracle(s, W, H, G, oracle.OracleConfig(**BAND))
-    # Coverage, live counts, image and T as everywhere. The gradients of the splats behind the
-    # 400 faint layers carry the FP32 error of the C' recurrence (Eqs. 5-6): C' loses about one
-    # rounding per layer, K eps |C| ~ 400 x 6e-8, against c T - C' of a few 1e-2 in Eq. 7, so
-    # about 1e-3 relative on their dL/dalpha; measured 2.2e-4 over all parameters.
-    e = _check(out, ref, grad_tol=1e-3)
+    ref = _oracle(s, W, H, G, ocfg)
+    e = _check(out, ref)
     ws = R.Workspace()
     p = R.prepare_2d(t(s.means2d), t(s.conics), t(s.opacities), t(s.rgb), t(s.depth), W, H, cfg, ws)
     f = R.raster_forward(p, cfg, ws)      # depth-split when the workspace allows it

@@ -65,3 +65,6 @@ def test_results_alone_equal_results_in_the_mix():
                 worst3d = max(worst3d, rel_l2(a["grads"][k].cpu().numpy(),
                                               b["grads"][k].cpu().numpy()))
     print("3D gradients, mix vs alone, worst rel-L2", worst3d)
+    # the served 3D gradients of a request are the same alone and in the mix within the FP16
+    # gradient limit (the requests' framebuffers are FP16)
+    assert worst3d <= 1e-2, worst3d

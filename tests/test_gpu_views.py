@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import rel_l2, t
+from tests.helpers import certain_grad, rel_l2, t
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -82,15 +82,21 @@ def test_batched_stages_match_one_view_calls(fmt, bg):
         assert e <= 1e-6, (k, e)
 
 
-def test_batched_chain_against_oracle():
+@pytest.mark.parametrize("mode", ["hybrid", "tile"])
+def test_batched_chain_against_oracle(mode):
     """GPU projection -> sort -> raster -> projection backward over three views in one call each,
     against the oracle's FP64 chain per view with its complex-step projection backward, summed
     over the views."""
     sc = synth.scene3d(20_000, seed=9)
     cams = _ring(3)
     V = len(cams)
-    G = np.stack([synth.image_grad(W, H, 60 + v) for v in range(V)])
-    cfg = R.RasterConfig()
+    ocfg = oracle.OracleConfig(beta=1e-5, beta_abs=2e-3, tau=1e-3)
+    # dL/dC zero at the pixels with a borderline decision (R19; up to 1.7 % of them here): there
+    # the FP32 rounding of the projected means alone flips decisions and moves the mean2d
+    # gradients of view 2 by 1.2e-4 (the same with the FP64 projection rounded to FP32)
+    G = np.stack([certain_grad(synth.image_grad(W, H, 60 + v),
+                               oracle.render_scene(sc, cams[v], cfg=ocfg)["amb"]) for v in range(V)])
+    cfg = R.RasterConfig(reduce_mode=mode)
     ws = R.Workspace()
     args = _args(sc)
     p = R.project(*args, cams, cfg, ws)
@@ -98,22 +104,28 @@ def test_batched_chain_against_oracle():
     b = R.raster_backward(p, f["fb"], t(G), cfg, ws)
     g3 = R.project_backward(*args, cams, cfg, b)
     torch.cuda.synchronize()
-    ocfg = oracle.OracleConfig(beta=1e-5, beta_abs=2e-3, tau=1e-3)
     ov = None
     for v in range(V):
         ref = oracle.render_scene(sc, cams[v], dL_dimg=G[v], cfg=ocfg)
         ok = ref["amb"] == 0
         d = np.abs(f["image"][v].cpu().numpy() - ref["img"])[:, ok].max()
-        print(f"[views] view {v} image max-abs (unflagged)", d, "flagged px", (~ok).mean())
-        assert d <= 1e-4
+        print(f"[views] {mode} view {v} image max-abs (unflagged)", d, "flagged px", (~ok).mean())
+        assert d <= 1e-5
         og = ref["grad"]
         r = oracle.preprocess_vjp(sc, cams[v], og[:, 0:2], og[:, 2:5], og[:, 6:9], og[:, 5])
+        # this view's share: the projection backward of the batched call's 2D gradients
+        gv = R.project_backward(*args, cams[v], cfg, {k: b[k][v] for k in G2D})
+        e2 = {k: rel_l2(b[k][v].cpu().numpy(), og[:, s]) for k, s in
+              (("means2d", slice(0, 2)), ("conics", slice(2, 5)), ("opacities", 5),
+               ("rgb", slice(6, 9)))}
+        e3 = {k: rel_l2(gv[k].cpu().numpy(), r[k]) for k in r}
+        print(f"[views] {mode} view {v} 2D", e2, "3D", e3)
         ov = r if ov is None else {k: ov[k] + r[k] for k in r}
     errs = {k: rel_l2(g3[k].cpu().numpy(), ov[k]) for k in ov}
     allg = rel_l2(np.concatenate([g3[k].cpu().numpy().reshape(-1) for k in ov]),
                   np.concatenate([ov[k].reshape(-1) for k in ov]))
-    print("[views] summed 3D gradient rel-L2", errs, "all", allg)
-    assert allg <= 1e-3
+    print(f"[views] {mode} summed 3D gradient rel-L2", errs, "all", allg)
+    assert max(max(errs.values()), allg) <= 1e-4, (errs, allg)
 
 
 def test_batched_autograd_sums_the_views():
