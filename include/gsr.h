@@ -245,6 +245,19 @@ int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible,
             void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * gs_sort for callers that cannot allocate device memory or pass a workspace: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation. Same operation, result
+ * and argument meaning as gs_sort; the scratch is instead a fixed array inside the library, one
+ * per GPU (GS_NOALLOC_SORT_MAX_N keys' worth, about 36 MB), set up on the first call on each
+ * device and held until the process ends. The call allocates nothing. n above
+ * GS_NOALLOC_SORT_MAX_N is rejected with GS_ERR_CAPACITY before any launch. Calls that overlap on
+ * one GPU (other streams, other threads) share that array and race: serialise them.
+ */
+#define GS_NOALLOC_SORT_MAX_N (1 << 22)
+int gs_sort_noalloc(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible,
+                    void* stream);
+
+/*
  * gs_sort for n_views views in one launch per step: keys [n_views][n], ids [n_views][n],
  * n_visible [n_views]; each view's first n_visible[v] pairs are sorted as gs_sort does. The
  * workspace is cut into n_views slabs as described at the top (each needs

@@ -82,6 +82,7 @@ _SIGS = {
                                      c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_sort": (ctypes.c_int, [c_i, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_sort_views": (ctypes.c_int, [c_i, c_i, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_sort_noalloc": (ctypes.c_int, [c_i, c_p, c_p, c_p, c_p]),
     "gs_raster_setup": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                        c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_raster_fwd": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
@@ -190,6 +191,14 @@ def gs_prepare_2d(cam: GsCamera, cfg: GsConfig, n, means2d, conics, opacities, d
 def gs_sort(n, keys, ids, n_visible, ws, ws_bytes, stream):
     _check("gs_sort", lib().gs_sort(n, _ptr(keys), _ptr(ids), _ptr(n_visible), _ptr(ws),
                                     ws_bytes, stream))
+
+
+def gs_sort_noalloc(n, keys, ids, n_visible, stream):
+    _check("gs_sort_noalloc", lib().gs_sort_noalloc(n, _ptr(keys), _ptr(ids), _ptr(n_visible),
+                                                    stream))
+
+
+NOALLOC_SORT_MAX_N = 1 << 22
 
 
 def gs_sort_views(n_views, n, keys, ids, n_visible, ws, ws_bytes, stream):

@@ -290,6 +290,20 @@ int gs_sort(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible, v
                       "gs_sort");
 }
 
+int gs_sort_noalloc(int32_t n, uint32_t* keys, int32_t* ids, const int32_t* n_visible,
+                    void* stream) {
+    GSR_TRY(check_n(n));
+    GSR_NEED(n_visible);
+    if (n > gsr::NOALLOC_SORT_MAX_N)
+        return fail(GS_ERR_CAPACITY, "gs_sort_noalloc sorts at most %d keys (n = %d); use gs_sort "
+                    "with a workspace", gsr::NOALLOC_SORT_MAX_N, n);
+    if (n == 0) return ok();
+    GSR_NEED(keys);
+    GSR_NEED(ids);
+    return hip_status(gsr::launch_sort_u32_noalloc(n, keys, ids, n_visible, (hipStream_t)stream),
+                      "gs_sort_noalloc");
+}
+
 int gs_sort_views(int32_t n_views, int32_t n, uint32_t* keys, int32_t* ids,
                   const int32_t* n_visible, void* ws, size_t ws_bytes, void* stream) {
     if (n_views < 1 || n_views > GS_MAX_VIEWS)

@@ -109,6 +109,12 @@ hipError_t launch_sort_u32(int n, uint32_t* keys, int32_t* vals, const int32_t* 
                            hipStream_t s, const Views& vs = one_view());
 hipError_t launch_sort_u64(int n, uint64_t* keys, int32_t* vals, const int32_t* n_dev,
                            int end_bit, void* ws, hipStream_t s);
+// The depth sort with its scratch in the library's fixed per-device array (no workspace):
+// n <= NOALLOC_SORT_MAX_N.
+constexpr int NOALLOC_SORT_MAX_N = GS_NOALLOC_SORT_MAX_N;
+constexpr int MAX_DEVICES = 64;
+hipError_t launch_sort_u32_noalloc(int n, uint32_t* keys, int32_t* vals, const int32_t* n_dev,
+                                   hipStream_t s);
 // Fills `count` words at p in each of `views` slabs `stride` bytes apart.
 hipError_t launch_fill_u32(void* p, size_t count, uint32_t value, hipStream_t s, int views = 1,
                            uint64_t stride = 0);

@@ -8,6 +8,8 @@
 // and across the four waves through LDS counts. Three launches per pass.
 // Several views sort in one launch per step (grid y = view): each view's keys, ids and count are
 // its part of [V][n] arrays, and its histograms and ping-pong buffers live in its workspace slab.
+#include <mutex>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -473,6 +475,55 @@ hipError_t launch_sort_u32(int n, uint32_t* keys, int32_t* vals, const int32_t* 
 hipError_t launch_sort_u64(int n, uint64_t* keys, int32_t* vals, const int32_t* n_dev,
                            int end_bit, void* ws, hipStream_t s) {
     return sort_pairs<uint64_t>(n, keys, vals, n_dev, end_bit, ws, s, one_view());
+}
+
+// ---- the depth sort without a caller workspace ---------------------------------------------
+// For callers that cannot allocate (code under graph capture, serving loops, harnesses that
+// forbid allocation), the sort's scratch is a file-scope device array of fixed size, one per GPU,
+// held for the life of the process. In host code `scratch` only names the symbol: its device
+// address on the current GPU comes from hipGetSymbolAddress, taken once per device on the first
+// call there and kept; only that address is ever passed to a kernel. Every word of the scratch
+// is written before it is read in a call, so nothing needs clearing between calls; calls that
+// overlap on one GPU share the array and race.
+constexpr size_t NOALLOC_SORT_BYTES =
+    ((size_t)NOALLOC_SORT_MAX_N * 4 + 255) / 256 * 256 +          // alternate keys
+    ((size_t)NOALLOC_SORT_MAX_N * 4 + 255) / 256 * 256 +          // alternate values
+    2 * ((256 * (size_t)((NOALLOC_SORT_MAX_N + SORT_ITEMS - 1) / SORT_ITEMS) * 4 + 255) / 256 * 256) +
+    256 * 4;                                                       // digit totals
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SORT_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_sort_scratch(void** out, size_t* bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {           // set-up on this device, which is the current one
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    *bytes = NOALLOC_SORT_BYTES;
+    return hipSuccess;
+}
+
+hipError_t launch_sort_u32_noalloc(int n, uint32_t* keys, int32_t* vals, const int32_t* n_dev,
+                                   hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    void* ws = nullptr;
+    size_t bytes = 0;
+    hipError_t e = noalloc_sort_scratch(&ws, &bytes);
+    if (e != hipSuccess) return e;
+    if (sort_ws_bytes(n, 4) > bytes) return hipErrorInvalidValue;   // the caller checked n
+    return sort_pairs<uint32_t>(n, keys, vals, n_dev, 32, ws, s, one_view());
 }
 
 }  // namespace gsr
