@@ -25,8 +25,15 @@ sys.path.insert(0, ROOT)
 # Algorithmic FLOPs per fragment of the method's own arithmetic:
 FLOP_FWD_PER_COVERED = 24   # alpha of one fragment + the blend of Eq. 2
 FLOP_BWD_PER_LIVE = 69      # alpha, Eqs. 3/5/6/7, the chain rule to 9 parameters, their reduction
-PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
+# FP32 vector peaks of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s
+# for one FP32 operation per lane and cycle; the published 157.3 counts the packed two-wide FP32
+# instructions, which this library's build disables, so 78.6 is the ceiling its kernels can reach.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# Framebuffer bytes of the method per fragment (the algorithmic bytes of the survey's roofline,
+# what a render target holding the state in memory would move): S = state bytes per pixel.
+STATE_BYTES = {"f32": 16, "f16": 8, "unorm16": 8, "bf16": 8, "unorm8": 4}
 
 
 def _parse():
@@ -35,16 +42,23 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
-    ap.add_argument("--formats", default="f16,f32")
+    ap.add_argument("--formats", default="f16,f32,unorm16")
     ap.add_argument("--reduce", default="tile")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-blocks", type=int, default=96)
-    ap.add_argument("--variants", action="store_true", help="also time reduce modes / fwd T-cull")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip Table 1's reduction modes, the X sweep and the forward T-cull")
+    ap.add_argument("--no-micro", action="store_true",
+                    help="skip the HBM-copy and FP32-atomic microbenchmarks")
+    ap.add_argument("--no-fit", action="store_true", help="skip the 300-step fitting run")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time the CPU oracle on whole frames (cfg1, cfg2) and a cfg3 sample, "
+                         "at all host threads and at one; prints a JSON line")
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-based baseline")
     ap.add_argument("--no-views", action="store_true",
                     help="skip the several-views-per-call measurement (fitting workload)")
-    ap.add_argument("--serve-requests", type=int, default=600,
-                    help="requests of the serving run (0: skip); 100 more are warmup")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="measured requests of each serving run (0: skip); 200 more are warmup")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-format-errors", action="store_true",
@@ -55,11 +69,11 @@ def _parse():
     return ap.parse_args()
 
 
-def _traffic(kernels):
-    """HBM bytes per launch of the given kernels (summed) from the committed PMC summary, if it
-    was taken with the current kernel sources; else None."""
+def _profile(name, kernels, field):
+    """Sum over the given kernels of `field` in the committed profile summary profiles/<name>, if
+    every entry was taken with the current kernel sources; else None."""
     from paper_2505_18764_amd import pmc
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -67,10 +81,15 @@ def _traffic(kernels):
     tot = 0.0
     for k in kernels:
         e = d.get(k)
-        if not e or e.get("source_hash") != h:
+        if not e or e.get("source_hash") != h or e.get(field) is None:
             return None
-        tot += e["bytes_per_launch"]
+        tot += e[field]
     return tot
+
+
+def _traffic(kernels):
+    """HBM bytes per launch of the given kernels (summed) from the committed PMC summary."""
+    return _profile("traffic.json", kernels, "bytes_per_launch")
 
 
 def format_error_table(g, g_ref):
@@ -134,6 +153,9 @@ def main():
                               "1M clustered Gaussians, 1600x1064, FP16 framebuffer",
                               note="Seven views: one warmup, one instrumented (the INSTR = true "
                                    "instances count fragments for the stats), five timed.")
+        return
+    if args.cpu_full:
+        cpu_full(args)
         return
     import torch
     import synth
@@ -259,35 +281,62 @@ def main():
     head = results[head_fmt]
     st = head["stats"]
     F, Lv = st["fwd_covered"], st["bwd_live"]
+    A = st["bwd_atomic_sets"]
     fwd_ms, bwd_ms = head["stages_ms"]["raster_fwd"], head["stages_ms"]["raster_bwd"]
+    S = STATE_BYTES[head_fmt]
+    micro = None if args.no_micro else micro_run(dev)
+    # the method's framebuffer bytes (Proc. 1's state loads and stores, the blend's read-modify-
+    # write, 4 bytes a channel for FP32, 2 for the 16-bit formats): forward F 2S; backward
+    # (F - L) s_T + L (2S + 12) + A 36 (culled fragments read T only; a live one reads and
+    # writes the state and reads dL/dC; 36 bytes per atomic set of nine gradients)
+    s_T = S // 4
+    alg_bytes = {"raster_fwd": F * 2 * S,
+                 "raster_bwd": (F - Lv) * s_T + Lv * (2 * S + 12) + A * 36}
     roof = {}
     for name, ms, flops, keys in (("raster_fwd", fwd_ms, F * FLOP_FWD_PER_COVERED, FWD_KERNELS),
                                   ("raster_bwd", bwd_ms, Lv * FLOP_BWD_PER_LIVE, BWD_KERNELS)):
         ach = flops / (ms * 1e-3) / 1e12
         tr = _traffic(keys) if head_fmt == "f16" else None
-        roof[name] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
-                      "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                      "traffic": None if tr is None else round(tr), "flops_per_launch": flops,
-                      "ms": round(ms, 4), "kernels": list(keys)}
+        issue = _profile("issue.json", keys[:1], "share") if head_fmt == "f16" else None
+        alg_gbs = alg_bytes[name] / (ms * 1e-3) / 1e9
+        r = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+             "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+             "traffic": None if tr is None else round(tr),
+             "peak_published_packed": PEAK_FP32_PACKED_TFLOPS,
+             "frac_of_published": round(ach / PEAK_FP32_PACKED_TFLOPS, 4),
+             "valu_issue_share": None if issue is None else round(issue, 3),
+             "flops_per_launch": flops, "ms": round(ms, 4), "kernels": list(keys),
+             "algorithmic_bytes": alg_bytes[name], "algorithmic_gbs": round(alg_gbs, 1),
+             "algorithmic_over_hbm_peak": round(alg_gbs / PEAK_HBM_GBS, 3),
+             "measured_hbm_gbs": None if tr is None else round(tr / (ms * 1e-3) / 1e9, 1),
+             "measured_hbm_frac": None if tr is None else round(tr / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        if micro:
+            r["hbm_copy_gbs_measured"] = micro["copy_gbs"]
+        roof[name] = r
+    if micro:
+        # the backward's atomics against the measured FP32-atomic throughput: each set adds
+        # nine values, first with a returning add, then (when its rounding error is not zero)
+        # a second add of that error
+        n_at = 9 * A
+        t_ret = n_at / micro["atomic_per_s"]["spread_return"]
+        t_plain = n_at / micro["atomic_per_s"]["spread"]
+        roof["raster_bwd"]["atomics"] = {
+            "sets": A, "returning_adds": n_at, "error_adds_at_most": n_at,
+            "bound_ms": round((t_ret + t_plain) * 1e3, 4),
+            "frac_of_kernel_time": round((t_ret + t_plain) * 1e3 / bwd_ms, 4),
+            "rate_per_s_measured": micro["atomic_per_s"]}
     dom = "raster_fwd" if fwd_ms >= bwd_ms else "raster_bwd"
 
     extra = {}
-    if args.variants:
-        for mode in ("naive", "quad", "wave", "hybrid", "hybrid_lane", "tile"):
-            r = run_format(head_fmt, mode, steps=max(3, args.steps // 4), warmup=1)
-            s = r["stats"]
-            extra[f"reduce_{mode}"] = {"raster_bwd_ms": r["stages_ms"]["raster_bwd"],
-                                       "atomic_rate": s["bwd_atomic_sets"] / max(1, s["bwd_live"])}
-        r = run_format(head_fmt, args.reduce, t_min_fwd=float(np.float32(1e-4)),
-                       steps=max(3, args.steps // 2), warmup=1)
-        extra["fwd_tcull_ms_per_view"] = r["ms_per_view"]
-        extra["fwd_tcull_stages_ms"] = r["stages_ms"]
+    if not args.no_variants:
+        extra["variants"] = variants_run(run_format, inp, cam, Gd, R, head_fmt, args)
 
     format_errors = None
     if not args.no_format_errors:
         format_errors = format_error_run(inp, cam, Gd, R, dev)
 
     views = None if args.no_views else views_run(dev)
+    fitting = None if args.no_fit else fitting_run(dev)
 
     serving = None
     if args.serve_requests > 0:
@@ -313,7 +362,8 @@ def main():
         "config": {"workload": f"{c3['n']} clustered 3D Gaussians (SH deg 3), {W}x{H}, "
                                f"fx={c3['fx']}, dL/dC~U[-1,1]; framebuffer {head_fmt}, "
                                f"reduction {args.reduce}, paper mode (no forward T-cull)",
-                   "fb_format": head_fmt, "n": c3["n"], "width": W, "height": H},
+                   "framebuffer": head_fmt, "arithmetic": "f32", "n": c3["n"], "width": W,
+                   "height": H},
         "views_per_s": round(1e3 / head["ms_per_view"], 2),
         "formats": {k: {"ms_per_view": round(v["ms_per_view"], 4),
                         "stages_ms": {s: round(x, 4) for s, x in v["stages_ms"].items()},
@@ -322,16 +372,18 @@ def main():
         "fragments": {"covered": F, "live": Lv, "n_visible": head["n_visible"],
                       "covered_per_s": round(F / (fwd_ms * 1e-3), 1),
                       "live_per_s": round(Lv / (bwd_ms * 1e-3), 1),
-                      "atomic_rate": round(st["bwd_atomic_sets"] / max(1, Lv), 5),
+                      "atomic_rate": round(A / max(1, Lv), 5),
                       "cohesion": round(st["bwd_cohesive"] / max(1, st["bwd_wave_reductions"] +
                                                                    st["bwd_quad_reductions"]), 4),
                       "stats": st},
         "roofline": dict(roof[dom], kernel=dom),
         "roofline_kernels": roof,
+        "microbench": micro,
         "workspace_bytes": head["ws_bytes"],
         "tile_baseline": tile,
         "format_errors": format_errors,
         "views_per_call": views,
+        "fitting": fitting,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -434,30 +486,161 @@ def views_run(dev, steps=10, warmup=2):
     return out
 
 
-def serving_run(n_requests, dev, warmup=100, rate=200.0):
+def micro_run(dev, reps=5):
+    """The measured ceilings: a 1 GiB copy with the library's own copy kernel (best of `reps`,
+    bytes read + written per second), and FP32 global atomic adds per second in three patterns
+    over a 64 MB slot buffer (the size of the gradient slots of 800k splats)."""
+    import torch
+    from paper_2505_18764_amd import _lib as L
+    st = torch.cuda.current_stream().cuda_stream
+    nb = 1 << 30
+    a = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = 1e9
+    for _ in range(reps):
+        ev[0].record()
+        L.gs_micro_copy(a, b, nb, st)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    del a, b
+    out = {"copy_bytes": nb, "copy_gbs": round(2 * nb / (best * 1e-3) / 1e9, 1)}
+    nslots = 1 << 24
+    slots = torch.zeros(nslots, dtype=torch.float32, device=dev)
+    per = 64
+    rates = {}
+    for mode in ("spread", "spread_return", "wave_same"):
+        L.gs_micro_atomic_f32(slots, nslots, 4, mode, st)          # warm
+        ev[0].record()
+        L.gs_micro_atomic_f32(slots, nslots, per, mode, st)
+        ev[1].record()
+        torch.cuda.synchronize()
+        rates[mode] = round(per * L.MICRO_THREADS / (ev[0].elapsed_time(ev[1]) * 1e-3), 0)
+    out["atomic_per_s"] = rates
+    out["atomic_slots_bytes"] = nslots * 4
+    return out
+
+
+def variants_run(run_format, inp, cam, Gd, R, fmt, args):
+    """Table 1's comparison on the benchmark view: the backward raster with each gradient
+    reduction (naive, quad, wave and hybrid with X = 0 (no threshold), 4 and 8, the lane pre-sum
+    and the tile reduction): ms of the gs_raster_bwd stage and atomic sets per live fragment;
+    then the whole view with the forward T-culled (NEXT-1)."""
+    import torch
+    dev = inp[0].device
+    cfg0 = R.RasterConfig(fb_format=fmt, reduce_mode="tile")
+    ws = R.Workspace(dev)
+    p = R.project(*inp, cam, cfg0, ws)
+    R.raster_setup(p, cfg0, ws)
+    f = R.raster_forward(p, cfg0, ws, reuse_setup=True)
+    out = {}
+    cases = [("naive", 8), ("quad", 8), ("wave", 0), ("wave", 4), ("wave", 8), ("hybrid", 0),
+             ("hybrid", 4), ("hybrid", 8), ("hybrid_lane", 8), ("tile", 8)]
+    for mode, X in cases:
+        cfg = R.RasterConfig(fb_format=fmt, reduce_mode=mode, reduce_threshold=X)
+        g2 = R.raster_backward(p, f["fb"], Gd, cfg, ws, reuse_setup=True)
+        stt = R.new_stats(dev)
+        R.raster_backward(p, f["fb"], Gd, cfg, ws, reuse_setup=True, stats=stt, out=g2)
+        torch.cuda.synchronize()
+        s = R.read_stats(stt)
+        reps = 2 if mode == "naive" else 5
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            R.raster_backward(p, f["fb"], Gd, cfg, ws, reuse_setup=True, out=g2)
+        ev[1].record()
+        torch.cuda.synchronize()
+        key = mode if mode in ("naive", "quad", "hybrid_lane", "tile") else f"{mode}_X{X}"
+        out[key] = {"raster_bwd_ms": round(ev[0].elapsed_time(ev[1]) / reps, 4),
+                    "atomic_rate": round(s["bwd_atomic_sets"] / max(1, s["bwd_live"]), 5)}
+    r = run_format(fmt, args.reduce, t_min_fwd=float(np.float32(1e-4)),
+                   steps=max(3, args.steps // 2), warmup=1)
+    out["fwd_tcull"] = {"ms_per_view": round(r["ms_per_view"], 4),
+                        "stages_ms": {k: round(v, 4) for k, v in r["stages_ms"].items()}}
+    return out
+
+
+def fitting_run(dev, steps=300):
+    """The fitting workload (500k Gaussians fitted to a hidden 500k scene over 8 ring cameras at
+    1280x720, Adam lr 1e-3, one view per step through the autograd Function): ms per step over
+    all 300 steps (device events), and the loss at the first and last step."""
+    import torch
+    import synth
+    from paper_2505_18764_amd import render as R
+    from paper_2505_18764_amd import train as TR
+    c = synth.CFG4
+    W, H = c["width"], c["height"]
+    cams = [synth.camera_ring(k, c["cameras"], width=W, height=H, fx=c["fx"])
+            for k in range(c["cameras"])]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    hidden = synth.scene3d(c["n_hidden"], seed=c["seed_hidden"])
+    cfg = R.RasterConfig(reduce_mode="tile")
+    ws = R.Workspace(dev)
+    with torch.no_grad():
+        targets = [R.rasterize_gaussians(t(hidden.means3d), t(hidden.scales), t(hidden.quats),
+                                         t(hidden.opacities), t(hidden.sh), cm, cfg, ws)[0].clone()
+                   for cm in cams]
+    sc = synth.scene3d(c["n_train"], seed=c["seed_train"])
+    params = TR.GaussianParams(t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh))
+    TR.fit(params, cams, targets, 5, cfg=cfg)                      # warm up the kernels
+    params = TR.GaussianParams(t(sc.means3d), t(sc.scales), t(sc.quats), t(sc.opacities), t(sc.sh))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hist = TR.fit(params, cams, targets, steps, cfg=cfg, log_every=steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"workload": f"{c['n_train']} Gaussians fitted to a hidden {c['n_hidden']} over "
+                        f"{c['cameras']} ring cameras, {W}x{H}, Adam lr 1e-3, one view per step, "
+                        "FP32 framebuffer, tile reduction",
+            "steps": steps, "ms_per_step": round(e0.elapsed_time(e1) / steps, 4),
+            "loss_first": round(hist[0][1], 6), "loss_last": round(hist[-1][1], 6)}
+
+
+def serving_run(n_requests, dev, warmup=200, rate=200.0, saturating_rate=3000.0):
     """Continuous-batching server on 16 resident scenes (50k-3M Gaussians), resolutions
-    640x480-1920x1080, Poisson arrivals at `rate`/s, 70 % FWD / 30 % FWD_BWD, FP16 framebuffer,
-    64 GB pool, 4 streams."""
+    640x480-1920x1080, 70 % FWD / 30 % FWD_BWD, FP16 framebuffer, 64 GB pool, 4 streams: the
+    specified Poisson stream at `rate`/s (warmup + n_requests), then an offered rate well above
+    what the server sustains, which measures its capacity and the latency under overload."""
     import synth
     from paper_2505_18764_amd import serve as S
     scenes = S.load_scenes(dev)
     ex = S.GpuExecutor(scenes, S.serving_cameras(synth.CFG5_RESOLUTIONS))
-    srv = S.Server(ex, 64 << 30, slots=4).start()
-    summ = S.run_load(srv, synth.serving_requests(n_requests + warmup, rate), warmup)
-    srv.stop()
-    summ.update(offered_rate_per_s=rate, requests=n_requests, warmup=warmup)
-    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+    out = {}
+    for name, r in (("spec", rate), ("saturating", saturating_rate)):
+        srv = S.Server(ex, 64 << 30, slots=4).start()
+        summ = S.run_load(srv, synth.serving_requests(n_requests + warmup, r), warmup)
+        srv.stop()
+        summ.update(offered_rate_per_s=r, requests=n_requests, warmup=warmup)
+        out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+    out["capacity_views_per_s"] = out["saturating"]["views_per_s"]
+    return out
 
 
-def cpu_baseline(sc, cam, G, blocks):
-    """The FP64 oracle timed on this host on a bounded sample of the same view: the projection of
-    all Gaussians, the raster forward + backward on `blocks` random 32x32 pixel blocks (all
-    Gaussians, seeded choice), and the projection backward on 2 % of the Gaussians, each scaled to
-    a full view."""
-    import oracle
-    # the host share of one GPU: OMP_NUM_THREADS where the launcher sets it, at most 16
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads():
+    """The host share of one GPU: OMP_NUM_THREADS where the launcher sets it, else the cores
+    this process may run on."""
     nth = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
-    nth = max(1, min(nth, 16))
+    return max(1, min(nth, len(os.sched_getaffinity(0))))
+
+
+def _oracle_view_sample(sc, cam, G, blocks, nth, seed=77):
+    """FP64 oracle seconds for one view, from a sample: the projection of all Gaussians, the raster
+    forward + backward on `blocks` random 32x32 blocks scaled to the frame, the projection
+    backward on 2 % of the Gaussians scaled to all."""
+    import oracle
+    import synth
     cfg = oracle.OracleConfig(nthreads=nth)
     t0 = time.perf_counter()
     pre = oracle.preprocess(sc, cam, cfg)
@@ -465,10 +648,9 @@ def cpu_baseline(sc, cam, G, blocks):
     order = oracle.visible_order(pre["keys"])
     m2, cn, rgb = (pre["means2d"].astype(np.float32), pre["conic"].astype(np.float32),
                    pre["rgb"].astype(np.float32))
-    g = np.random.default_rng(77)
+    g = np.random.default_rng(seed)
     W, H = cam.width, cam.height
-    t_r = 0.0
-    px = 0
+    t_r, px = 0.0, 0
     for _ in range(blocks):
         x0, y0 = int(g.integers(0, W - 32)), int(g.integers(0, H - 32))
         t0 = time.perf_counter()
@@ -477,20 +659,96 @@ def cpu_baseline(sc, cam, G, blocks):
         t_r += time.perf_counter() - t0
         px += 32 * 32
     sub = g.choice(sc.n, size=max(1, sc.n // 50), replace=False)
-    import synth
     s2 = synth.Scene(means3d=sc.means3d[sub], scales=sc.scales[sub], quats=sc.quats[sub],
                      opacities=sc.opacities[sub], sh=sc.sh[sub], sh_degree=sc.sh_degree)
     gg = g.normal(size=(len(sub), 9))
     t0 = time.perf_counter()
     oracle.preprocess_vjp(s2, cam, gg[:, 0:2], gg[:, 2:5], gg[:, 6:9], gg[:, 5], cfg)
     t_vjp = (time.perf_counter() - t0) * sc.n / len(sub)
-    total_s = t_pre + t_r * (W * H / px) + t_vjp
-    return {"value": round(total_s * 1e3, 1), "unit": "ms/view", "cores": nth, "kind": "oracle",
-            "sample": f"FP64 oracle: projection of all {sc.n} Gaussians ({t_pre:.2f} s); raster "
-                      f"fwd+bwd on {blocks} random 32x32 blocks ({px} px, {t_r:.2f} s) scaled by "
-                      f"{W * H / px:.0f}x; projection backward on {len(sub)} Gaussians scaled by "
-                      f"{sc.n / len(sub):.0f}x"}
+    total = t_pre + t_r * (W * H / px) + t_vjp
+    return total, dict(t_pre=t_pre, t_raster=t_r, px=px, scale=W * H / px, t_vjp=t_vjp,
+                       n_sub=len(sub))
 
 
+def _oracle_full_2d(s, W, H, G, nth):
+    import oracle
+    t0 = time.perf_counter()
+    oracle.raster(s.means2d, s.conics, s.opacities, s.rgb, oracle.depth_order(s.depth), W, H,
+                  dL_dimg=G, cfg=oracle.OracleConfig(nthreads=nth))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(sc, cam, G, blocks):
+    """The FP64 oracle on this host: the benchmark view from a bounded sample (`blocks` 32x32
+    blocks at all host threads, a quarter of them at one thread), and the whole 1000-splat 128x128
+    2D view (cfg1) at both thread counts. Times are scaled to ms per view."""
+    import synth
+    nth = _host_threads()
+    tot_n, d_n = _oracle_view_sample(sc, cam, G, blocks, nth)
+    b1 = max(4, blocks // 4)
+    tot_1, d_1 = _oracle_view_sample(sc, cam, G, b1, 1, seed=78)
+    c1 = synth.CFG1
+    s1 = synth.splats2d(n=c1["n"], width=c1["width"], height=c1["height"], seed=c1["seed"])
+    G1 = synth.image_grad(c1["width"], c1["height"], 31)
+    cfg1_n = _oracle_full_2d(s1, c1["width"], c1["height"], G1, nth)
+    cfg1_1 = _oracle_full_2d(s1, c1["width"], c1["height"], G1, 1)
+    return {"value": round(tot_n * 1e3, 1), "unit": "ms/view", "cores": nth, "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "sample": f"FP64 oracle, benchmark view: projection of all {sc.n} Gaussians "
+                      f"({d_n['t_pre']:.2f} s); raster fwd+bwd on {blocks} random 32x32 blocks "
+                      f"({d_n['px']} px, {d_n['t_raster']:.2f} s) scaled by {d_n['scale']:.0f}x; "
+                      f"projection backward on {d_n['n_sub']} Gaussians scaled by "
+                      f"{sc.n / d_n['n_sub']:.0f}x",
+            "stages_s": {"projection": round(d_n["t_pre"], 3),
+                         "raster_fwd_bwd": round(d_n["t_raster"] * d_n["scale"], 2),
+                         "projection_bwd": round(d_n["t_vjp"], 2),
+                         "note": "the projection and its complex-step backward are numpy (one "
+                                 "thread whatever `cores` says); the raster is the C oracle on "
+                                 "`cores` OpenMP threads"},
+            "one_thread": {"value": round(tot_1 * 1e3, 1), "unit": "ms/view", "cores": 1,
+                           "sample": f"as above with {b1} blocks",
+                           "stages_s": {"projection": round(d_1["t_pre"], 3),
+                                        "raster_fwd_bwd": round(d_1["t_raster"] * d_1["scale"], 2),
+                                        "projection_bwd": round(d_1["t_vjp"], 2)}},
+            "cfg1_full_frame_ms": {"cores_all": round(cfg1_n * 1e3, 2),
+                                   "cores_1": round(cfg1_1 * 1e3, 2)}}
+
+
+def cpu_full(args):
+    """The oracle on whole frames: cfg1 (1000 splats, 128x128) and cfg2 (200k Gaussians,
+    1024x768: projection, raster forward + backward of the whole image, projection backward), at
+    all host threads and at one; and the benchmark view from a 96-block sample at both. Host
+    work only (no GPU)."""
+    import oracle
+    import synth
+    nth = _host_threads()
+    out = {"cpu_model": _cpu_model(), "threads_all": nth}
+    c1 = synth.CFG1
+    s1 = synth.splats2d(n=c1["n"], width=c1["width"], height=c1["height"], seed=c1["seed"])
+    G1 = synth.image_grad(c1["width"], c1["height"], 31)
+    out["cfg1_full_s"] = {str(k): round(_oracle_full_2d(s1, c1["width"], c1["height"], G1, k), 4)
+                          for k in (nth, 1)}
+    c2 = synth.CFG2
+    sc2 = synth.scene3d(c2["n"], seed=c2["seed"])
+    cam2 = synth.camera_front(c2["width"], c2["height"], c2["fx"])
+    G2 = synth.image_grad(c2["width"], c2["height"], c2["grad_seed"])
+    out["cfg2_full_s"] = {}
+    for k in (nth, 1):
+        cfg = oracle.OracleConfig(nthreads=k)
+        t0 = time.perf_counter()
+        r = oracle.render_scene(sc2, cam2, dL_dimg=G2, cfg=cfg)
+        og = r["grad"]
+        oracle.preprocess_vjp(sc2, cam2, og[:, 0:2], og[:, 2:5], og[:, 6:9], og[:, 5], cfg)
+        out["cfg2_full_s"][str(k)] = round(time.perf_counter() - t0, 2)
+        print(json.dumps({"cfg2_threads": k, "s": out["cfg2_full_s"][str(k)]}), flush=True)
+    c3 = synth.CFG3
+    sc3 = synth.scene3d(c3["n"], seed=c3["seed"])
+    cam3 = synth.camera_front(c3["width"], c3["height"], c3["fx"])
+    G3 = synth.image_grad(c3["width"], c3["height"], c3["grad_seed"])
+    out["cfg3_sampled_ms_per_view"] = {}
+    for k, blocks in ((nth, 96), (1, 24)):
+        tot, d = _oracle_view_sample(sc3, cam3, G3, blocks, k)
+        out["cfg3_sampled_ms_per_view"][str(k)] = {"ms": round(tot * 1e3, 1), "blocks": blocks}
+    print(json.dumps(out), flush=True)
 if __name__ == "__main__":
     main()

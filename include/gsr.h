@@ -380,6 +380,29 @@ int gs_raster_debug_schedule(const gs_config* cfg, int32_t n, int32_t width, int
                              int32_t* bwd_order, int32_t* item_order, int32_t* items,
                              int64_t* n_items, void* stream);
 
+/* ---- Microbenchmarks: the measured ceilings of the raster's bounds (compute nothing of the
+ * method). Both enqueue one kernel on `stream` and return at once; time them with events. ---- */
+
+/* Copies `bytes` (a multiple of 16; src and dst 16-byte aligned, not overlapping) from src to dst
+ * with 16-byte loads and stores over a grid-stride loop: the HBM stream bandwidth a kernel of
+ * this library can reach. */
+int gs_micro_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+#define GS_MICRO_THREADS (1 << 20)
+enum gs_micro_atomic_mode {
+    GS_MICRO_ATOMIC_SPREAD = 0,         /* consecutive lanes add to consecutive words (the
+                                           backward's gradient flush); no value returned */
+    GS_MICRO_ATOMIC_SPREAD_RETURN = 1,  /* the same, each add returning the old value (the first
+                                           add of the flush's compensated pair) */
+    GS_MICRO_ATOMIC_WAVE_SAME = 2       /* the 64 lanes of a wave add to one word (per-fragment
+                                           atomics of one splat across a wave) */
+};
+/* adds_per_thread x GS_MICRO_THREADS FP32 atomic adds of 1/64 into slots[0 .. nslots) (device
+ * memory, nslots a power of two, 64 .. 2^30) in the pattern `mode`. The slots are not cleared:
+ * each one gains (adds it received) / 64. */
+int gs_micro_atomic_f32(float* slots, int64_t nslots, int32_t adds_per_thread, int32_t mode,
+                        void* stream);
+
 /* ---- Comparison design: tile-based software rasterization (Sec. 2.1.3-2.1.4) ----------------
  *
  * 16x16-pixel tiles. Each visible splat is duplicated into one (tile, depth key) pair per tile its

@@ -98,6 +98,8 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_uint32), c_p]),
     "gs_raster_debug_schedule": (ctypes.c_int, [ctypes.POINTER(GsConfig), c_i, c_i, c_i, c_p,
                                                 c_sz, c_p, c_p, c_p, c_p, c_p, c_p]),
+    "gs_micro_copy": (ctypes.c_int, [c_p, c_p, c_sz, c_p]),
+    "gs_micro_atomic_f32": (ctypes.c_int, [c_p, ctypes.c_int64, c_i, c_i, c_p]),
     "gs_tile_workspace_size": (c_sz, [c_i, ctypes.c_int64, c_i, c_i]),
     "gs_tile_prepare": (ctypes.c_int, [ctypes.POINTER(GsCamera), ctypes.POINTER(GsConfig), c_i,
                                        c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
@@ -255,6 +257,20 @@ def gs_raster_debug_schedule(cfg: GsConfig, n, width, height, ws, ws_bytes, fwd_
     _check("gs_raster_debug_schedule", lib().gs_raster_debug_schedule(
         ctypes.byref(cfg), n, width, height, _ptr(ws), ws_bytes, _ptr(fwd_order), _ptr(bwd_order),
         _ptr(item_order), _ptr(items), _ptr(n_items), stream))
+
+
+MICRO_THREADS = 1 << 20
+MICRO_ATOMIC = {"spread": 0, "spread_return": 1, "wave_same": 2}
+
+
+def gs_micro_copy(src, dst, nbytes, stream):
+    _check("gs_micro_copy", lib().gs_micro_copy(_ptr(src), _ptr(dst), nbytes, stream))
+
+
+def gs_micro_atomic_f32(slots, nslots, adds_per_thread, mode, stream):
+    m = MICRO_ATOMIC[mode] if isinstance(mode, str) else mode
+    _check("gs_micro_atomic_f32", lib().gs_micro_atomic_f32(_ptr(slots), nslots, adds_per_thread,
+                                                            m, stream))
 
 
 def gs_tile_workspace_size(n, pair_capacity, width, height) -> int:

@@ -21,12 +21,13 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster.hip", "tile.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster.hip", "tile.hip", "micro.hip"]
 # The ordered path's atomics stay as written: its kernels reduce before every atomic (and its
 # paper-mode comparisons must issue exactly the atomics they count), so the compiler's
 # lane-combining loops would only cost instructions. The tile-based baseline keeps the
 # compiler's default, which merges its per-fragment atomics to one address within a wave.
-SOURCE_FLAGS = {"raster.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+SOURCE_FLAGS = {"raster.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+                "micro.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -454,6 +454,33 @@ int gs_raster_debug_schedule(const gs_config* cfg, int32_t n, int32_t width, int
                       "gs_raster_debug_schedule");
 }
 
+int gs_micro_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (bytes == 0) return ok();
+    GSR_NEED(src);
+    GSR_NEED(dst);
+    if (bytes % 16 || ((uintptr_t)src) % 16 || ((uintptr_t)dst) % 16)
+        return fail(GS_ERR_INVALID_ARGUMENT, "gs_micro_copy: 16-byte sizes and alignment");
+    const char* a = (const char*)src;
+    const char* b = (const char*)dst;
+    if (a < b + bytes && b < a + bytes)
+        return fail(GS_ERR_INVALID_ARGUMENT, "gs_micro_copy: overlapping buffers");
+    return hip_status(gsr::launch_micro_copy(src, dst, bytes, (hipStream_t)stream), "gs_micro_copy");
+}
+
+int gs_micro_atomic_f32(float* slots, int64_t nslots, int32_t adds_per_thread, int32_t mode,
+                        void* stream) {
+    GSR_NEED(slots);
+    if (nslots < 64 || nslots > ((int64_t)1 << 30) || (nslots & (nslots - 1)))
+        return fail(GS_ERR_INVALID_ARGUMENT, "gs_micro_atomic_f32: nslots a power of two in 64..2^30");
+    if (adds_per_thread < 0 || adds_per_thread > 4096)
+        return fail(GS_ERR_INVALID_ARGUMENT, "gs_micro_atomic_f32: adds_per_thread in 0..4096");
+    if (mode < GS_MICRO_ATOMIC_SPREAD || mode > GS_MICRO_ATOMIC_WAVE_SAME)
+        return fail(GS_ERR_INVALID_ARGUMENT, "gs_micro_atomic_f32: unknown mode %d", mode);
+    return hip_status(gsr::launch_micro_atomic(slots, (size_t)nslots, adds_per_thread, mode,
+                                               (hipStream_t)stream),
+                      "gs_micro_atomic_f32");
+}
+
 // ---- tile-based comparison rasterizer --------------------------------------------------------
 
 size_t gs_tile_workspace_size(int32_t n, int64_t pair_capacity, int32_t width, int32_t height) {

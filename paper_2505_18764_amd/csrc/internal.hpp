@@ -142,6 +142,10 @@ hipError_t launch_raster_bwd(const gs_config& cfg, int width, int height, int n,
                              const Views& vs = one_view());
 
 
+// ---- microbenchmarks ---------------------------------------------------------------------------
+hipError_t launch_micro_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_micro_atomic(float* slots, size_t nslots, int per, int mode, hipStream_t s);
+
 // ---- tile-based comparison rasterizer ------------------------------------------------------
 size_t tile_ws_bytes(int n, size_t cap, int W, int H);
 hipError_t launch_tile_prepare(const gs_config& cfg, int W, int H, int n, const int32_t* ids,

@@ -184,7 +184,12 @@ def issue_summary(path: str, out_md: str, command: str, workload: str, top: int 
                      f"{v.get('SQ_INSTS_VALU_TRANS_F32', 0) / 1e6:.1f} | "
                      f"{v.get('SQ_INSTS_SALU', 0) / 1e6:.1f} | {v.get('SQ_INSTS_LDS', 0) / 1e6:.1f} | "
                      f"{share:.2f} | {share_nt:.2f} |")
-    lines += ["", f"Source hash of the kernels measured: `{source_hash()}`."]
+    h = source_hash()
+    lines += ["", f"Source hash of the kernels measured: `{h}`."]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    js = {k: dict(v, source_hash=h) for k, v in res.items()}
+    js["_command"] = command
+    with open(os.path.join(os.path.dirname(out_md), "issue.json"), "w") as fh:
+        json.dump(js, fh, indent=1)
     return res
