@@ -185,8 +185,10 @@ def main():
     Gd = t(G)
     torch.cuda.synchronize()
 
-    def run_format(fmt, reduce_mode, t_min_fwd=0.0, steps=args.steps, warmup=args.warmup):
-        cfg = R.RasterConfig(fb_format=fmt, reduce_mode=reduce_mode, t_min_fwd=t_min_fwd)
+    def run_format(fmt, reduce_mode, t_min_fwd=0.0, steps=args.steps, warmup=args.warmup,
+                   composite_all=False):
+        cfg = R.RasterConfig(fb_format=fmt, reduce_mode=reduce_mode, t_min_fwd=t_min_fwd,
+                             composite_all=composite_all)
         ws = R.Workspace(dev)
         # preallocated outputs: the timed steps allocate nothing
         p = R.project(*inp, cam, cfg, ws)
@@ -526,7 +528,8 @@ def variants_run(run_format, inp, cam, Gd, R, fmt, args):
     """Table 1's comparison on the benchmark view: the backward raster with each gradient
     reduction (naive, quad, wave and hybrid with X = 0 (no threshold), 4 and 8, the lane pre-sum
     and the tile reduction): ms of the gs_raster_bwd stage and atomic sets per live fragment;
-    then the whole view with the forward T-culled (NEXT-1)."""
+    then the whole view with the forward T-culled (NEXT-1), and with the forward compositing
+    every covered fragment (no saturation exit)."""
     import torch
     dev = inp[0].device
     cfg0 = R.RasterConfig(fb_format=fmt, reduce_mode="tile")
@@ -558,6 +561,10 @@ def variants_run(run_format, inp, cam, Gd, R, fmt, args):
                    steps=max(3, args.steps // 2), warmup=1)
     out["fwd_tcull"] = {"ms_per_view": round(r["ms_per_view"], 4),
                         "stages_ms": {k: round(v, 4) for k, v in r["stages_ms"].items()}}
+    # every covered fragment composited (no saturation exit; depth split): the same image
+    r = run_format(fmt, args.reduce, steps=max(3, args.steps // 2), warmup=1, composite_all=True)
+    out["composite_all"] = {"ms_per_view": round(r["ms_per_view"], 4),
+                            "stages_ms": {k: round(v, 4) for k, v in r["stages_ms"].items()}}
     return out
 
 

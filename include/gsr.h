@@ -106,9 +106,12 @@ enum gs_reduce_mode {
 
 enum gs_flags {
     GS_FLAG_STATS = 1,          /* count fragments, atomics and reductions into gs_stats */
-    GS_FLAG_REUSE_SETUP = 2     /* gs_raster_fwd / gs_raster_bwd: the workspace already holds the
+    GS_FLAG_REUSE_SETUP = 2,    /* gs_raster_fwd / gs_raster_bwd: the workspace already holds the
                                    raster setup (see gs_raster_setup) for these exact inputs,
                                    image size, alpha_min and fb_format; skip rebuilding it */
+    GS_FLAG_COMPOSITE_ALL = 4   /* gs_raster_fwd: composite every covered fragment even where the
+                                   stored state can no longer change (see gs_raster_fwd); same
+                                   image, T a little lower; for comparisons */
 };
 
 /* Pinhole camera. viewmat is the 3x4 world->camera matrix [R|t], row-major; the camera looks
@@ -291,6 +294,11 @@ int gs_raster_setup(const gs_camera* cam, const gs_config* cfg, int32_t n,
  * cfg->t_min_fwd > 0); at the end C += T cfg->background (T stays the splats' product). The
  * per-pixel state (C, T) is rounded to cfg->fb_format per cfg->fb_round
  * and written to the framebuffer `fb` (gs_framebuffer_size bytes, [H][W][4] in that format).
+ * Saturation exit (state at rest, no counters requested, GS_FLAG_COMPOSITE_ALL not set): a
+ * pixel block stops compositing once each of its pixels has T <= 1e-6 and, in FP32, no fragment
+ * of the view can change its colour any more (C_ch + 2 T max|c| == C_ch): the stored colour is
+ * then bit-identical to compositing every fragment, and T within 1e-6 of its product over all
+ * of them. With counters (stats, out_coverage) every covered fragment is composited and counted.
  * In the unorm formats splat colours saturate to 1 (Sec. 3.3).
  * Inputs [n] by splat id: means2d [n,2], conics [n,3], opacities [n], rgb [n,3];
  *   sorted_ids [n] (a permutation of 0..n-1, as gs_sort leaves it), n_visible [1] device int32.

@@ -85,7 +85,7 @@ int check_cfg(const gs_config* c) {
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown reduce_mode %d", c->reduce_mode);
     if (c->reduce_threshold < 0 || c->reduce_threshold > 64)
         return fail(GS_ERR_INVALID_ARGUMENT, "reduce_threshold %d outside 0..64", c->reduce_threshold);
-    if (c->flags & ~(GS_FLAG_STATS | GS_FLAG_REUSE_SETUP))
+    if (c->flags & ~(GS_FLAG_STATS | GS_FLAG_REUSE_SETUP | GS_FLAG_COMPOSITE_ALL))
         return fail(GS_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", c->flags);
     for (int k = 0; k < 3; ++k)
         if (!isfinite(c->background[k]))

@@ -56,7 +56,9 @@ struct RasterWs {
     float* grad;       // [n * GRAD_STRIDE] (backward only)
     float* bgpart;     // [tiles][4] per-tile dL/dbackground partial sums (backward only)
     unsigned long long* counters;  // [16] planner scratch: [0] the work-item count, [1] the status word
-    uint32_t* status;  // device status word (gs_status_bits), cleared by every raster setup
+    uint32_t* status;  // device status word (gs_status_bits), cleared by every raster setup;
+                       // status[2] holds the bits of the view's largest |colour| (the forward's
+                       // saturation exit)
     uint32_t* weights; // [tiles] splat count per tile
     int32_t* order;    // [tiles] tiles, heaviest first
     uint32_t* bwd_w;   // [tiles] the backward's walk length per tile (forward's estimate)

@@ -340,7 +340,10 @@ __global__ __launch_bounds__(256) void k_raster_pack(
     if (blockIdx.x == 0) {               // a new setup: weights and the status word start at 0
         weights = view_bytes(weights, vws);
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) weights[t] = 0u;
-        if (threadIdx.x == 0) *view_bytes(status, vws) = 0u;
+        if (threadIdx.x == 0) {
+            *view_bytes(status, vws) = 0u;
+            *view_bytes(status + 2, vws) = 0u;      // the largest |colour| (k_raster_setup)
+        }
     }
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= n) return;
@@ -426,6 +429,7 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
 #pragma unroll
     for (int j = 0; j < SETUP_PER_THREAD; ++j)
         if (ids[j] >= 0) q[j] = idrec[ids[j]];
+    float cmax_l = 0.f;
     __shared__ uint32_t s_first[SETUP_NT + 1];   // exclusive scan of the round's pair counts
     __shared__ uint2 s_rect[SETUP_NT];
     __shared__ uint32_t s_wtot[SETUP_NT / 64];
@@ -440,6 +444,11 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
             rr = q[j].rect;
         }
         if (p < n) rect[p] = rr;
+        if (rr.x != NO_TILE_X) {             // the view's largest |colour| (saturation exit)
+            const float cm = fmaxf(fmaxf(fabsf(q[j].r.b.z), fabsf(q[j].r.b.w)),
+                                   fabsf(__uint_as_float(q[j].r.c.x)));
+            cmax_l = fmaxf(cmax_l, cm);
+        }
         const uint32_t tx0 = rr.x & 0xFFFFu, tx1 = rr.x >> 16;
         const uint32_t ty0 = rr.y & 0xFFFFu, ty1 = rr.y >> 16;
         const uint32_t cnt = rr.x != NO_TILE_X ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0u;
@@ -494,6 +503,18 @@ __global__ __launch_bounds__(SETUP_NT) void k_raster_setup(
             }
         }
         __syncthreads();                   // s_first / s_rect are rewritten by the next round
+    }
+    {   // the workgroup's largest |colour|, one atomic per workgroup (non-negative floats order
+        // as their bits)
+        __shared__ float s_cm[SETUP_NT / 64];
+        float m = cmax_l;
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if (lane == 0) s_cm[wave] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w2 = 1; w2 < SETUP_NT / 64; ++w2) m = fmaxf(m, s_cm[w2]);
+            if (m > 0.f) atomicMax(view_bytes(status, vws) + 2, __float_as_uint(m));
+        }
     }
     if (in_lds)
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
@@ -718,6 +739,14 @@ struct Half32 {
 // compiler for 7 waves per SIMD (<= 72 VGPRs), which measured faster than 6 with fewer spills.
 // MULTI: a launch over several views (grid y). Its per-view pointers cost scalar registers that
 // the one-view instances, whose walk pointers stay plain kernel arguments, do not pay.
+//
+// Saturation exit (at-rest state, no counters, `freeze` set): after each staged batch a wave
+// drops the sub-blocks in which no pixel's stored state can change any more: T <= 1e-6 and, in
+// FP32, C_ch + 2 T c_max == C_ch for each channel, c_max the view's largest |colour|. A later
+// fragment adds T alpha c with |T alpha c| <= T c_max, which rounds to C under that condition
+// (rounding is monotone in the addend), so C is bit-identical to compositing every covered
+// fragment and T is within 1e-6 of its final value. The walk of a tile ends when all its
+// sub-blocks are done. The instances with counters walk every fragment (exact coverage counts).
 template <int RFMT, bool TCULL, bool INSTR, bool MULTI>
 __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
@@ -728,9 +757,13 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     float amin, float amax, float tmin, float tsat, float bg0, float bg1, float bg2, int fb_fmt,
     void* __restrict__ fb, float* __restrict__ out_rgb, float* __restrict__ out_T,
     int32_t* __restrict__ out_cov, unsigned long long* __restrict__ stats,
-    uint32_t* __restrict__ bwd_w, uint32_t* __restrict__ status, uint64_t vws) {
+    uint32_t* __restrict__ bwd_w, uint32_t* __restrict__ status, int freeze_on, uint64_t vws) {
     __shared__ Walk<ROUND_CHUNKS> w;
     status = view_bytes(status, vws);
+    constexpr bool FREEZE = RFMT < 0 && !TCULL && !INSTR;
+    constexpr bool ALIVE = TCULL || FREEZE;        // sub-blocks can drop out of the walk
+    const bool freeze = FREEZE && freeze_on;
+    const float cm2 = freeze ? 2.f * __uint_as_float(status[2]) : 0.f;
     if constexpr (MULTI) {   // this view's walk state (its outputs are located at the write-back)
         nvis_ptr = view_at(nvis_ptr, 1);
         bwd_w = view_bytes(bwd_w, vws);
@@ -821,7 +854,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
             stage(w, rec, n, b0, total, tid, status);
             __syncthreads();
             const int m = min(BATCH, total - b0);
-            if (!TCULL || alive) {
+            if (!ALIVE || alive) {
                 const int nlist = cull_batch(w, m, wave, lane, lt, cx0, cy0);
                 if (!wsat) wl += (uint32_t)nlist;
                 if (INSTR) nwalk += (uint32_t)nlist;
@@ -841,7 +874,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                         const float cb = __uint_as_float(Cw.x);
                         // the exponent's row part (log2 o folded in) for the lane's two pixel rows
                         float dxs[2], dys[2], er[2];
-                        const uint32_t sb = (ent >> 8) & (TCULL ? alive : 0xFu);
+                        const uint32_t sb = (ent >> 8) & (ALIVE ? alive : 0xFu);
                         alpha_rows(A, B, __uint_as_float(Cw.y), px, py, dxs, dys, er);
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
@@ -891,11 +924,24 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
                 for (int s = 0; s < 4; ++s) a = a || (valid[s] && (float)T[s] >= tsat);
                 wsat = ballot(a) == 0ull;
             }
-            if (TCULL && lane == 0) w.alive[wave] = (int)alive;
+            if (FREEZE && freeze) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    if (!((alive >> s) & 1u)) continue;
+                    const float Ts = (float)T[s];
+                    const float inc = cm2 * Ts;
+                    const bool done = !valid[s] ||
+                                      (Ts <= 1e-6f && (float)C[s][0] + inc == (float)C[s][0] &&
+                                       (float)C[s][1] + inc == (float)C[s][1] &&
+                                       (float)C[s][2] + inc == (float)C[s][2]);
+                    if (!ballot(!done)) alive &= ~(1u << s);
+                }
+            }
+            if (ALIVE && lane == 0) w.alive[wave] = (int)alive;
             __syncthreads();
-            if (TCULL && !(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3])) { stop = true; break; }
+            if (ALIVE && !(w.alive[0] | w.alive[1] | w.alive[2] | w.alive[3])) { stop = true; break; }
         }
-        if (TCULL && stop) break;
+        if (ALIVE && stop) break;
     }
     // A walk from the front of the tile knows the backward's work on it: the largest wave count
     // (the waves run side by side). A first depth segment that leaves some wave unsaturated
@@ -1234,8 +1280,62 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                         // cullingFlag: splat boundary (alpha < 1/255, tested on the unclamped alpha
                         // as in the forward), then T-Culling (T < 1e-4)
                         const bool live = valid[s] && araw >= amin && T[s] >= tmin;
-                        // the fragment's nine gradients: added straight into the lane's sums in the
-                        // tile reduction, else kept for the per-fragment reduction
+                        if constexpr (TILEM) {
+                            // Straight-line body: a lane that is not live takes alpha = 0 and a
+                            // zero dL/dalpha, so every sum and the state update leave it as it is.
+                            // (Behind divergent branches the compiler copied the nine sums at
+                            // every join.) Live lanes do the operations of the paper modes below.
+                            if (ballot(live)) {
+                                acc_live = true;
+                                const float Ti = T[s];
+                                const float alm = live ? al : 0.f;
+                                const float wt = alm * Ti;
+                                // Eq. 3: dL/dc = dL/dC alpha T
+                                acc[6] = fmaf(G[s][0], wt, acc[6]);
+                                acc[7] = fmaf(G[s][1], wt, acc[7]);
+                                acc[8] = fmaf(G[s][2], wt, acc[8]);
+                                // Eq. 7, and the final transmittance's share
+                                const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) +
+                                                  G[s][1] * (cg * Ti - Cp[s][1]) +
+                                                  G[s][2] * (cb * Ti - Cp[s][2]) - gTT[s]) *
+                                                 __builtin_amdgcn_rcpf(1.f - al);
+                                // Eqs. 5, 6
+                                Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
+                                Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
+                                Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
+                                if constexpr (RFMT == FB_F16) T[s] = fmaf(-Ti, alm, Ti);
+                                else T[s] = Ti - wt;
+                                if constexpr (RFMT >= 0) {   // idempotent on unchanged lanes
+                                    Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
+                                    Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
+                                    Cp[s][2] = fb_round<RFMT>(Cp[s][2]);
+                                    T[s] = fb_round<RFMT>(T[s]);
+                                }
+                                // bwd_diff (zero through a clamped alpha), as in the paper modes:
+                                // h = dL/dalpha alpha; dalpha/do = exp(-q/2); dL/dq = -h / 2;
+                                // dp/dd in the factored form (a' u, k a' u + d' dy)
+                                const float h = (live && araw < amax) ? ga * araw : 0.f;
+                                acc[5] = fmaf(h, inv_o, acc[5]);
+                                const float gq = -0.5f * h;
+                                const float gm = -2.f * (h * (1.0f / LOG2E));
+                                const float gy = fmaf(A.w, au, B.x * dy);
+                                acc[0] = fmaf(gm, au, acc[0]);
+                                acc[1] = fmaf(gm, gy, acc[1]);
+                                const float gdx = gq * dx;
+                                acc[2] = fmaf(gdx, dx, acc[2]);
+                                acc[3] = fmaf(2.f * gdx, dy, acc[3]);
+                                acc[4] = fmaf(gq * dy, dy, acc[4]);
+                            }
+                            if (INSTR) {
+                                cnt.evaluated += valid[s];
+                                cnt.live += live;
+                                nlive[s] += live;
+                            }
+                            if ((i & 3) == 3 || i0 + i + 1 == nlist)
+                                if (!ballot(valid[s] && T[s] >= tmin)) alive &= ~(1u << s);
+                            continue;
+                        }
+                        // the fragment's nine gradients, kept for the per-fragment reduction
                         float g[9];
                         if constexpr (!TILEM) {
 #pragma unroll
@@ -1542,7 +1642,7 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
     const int V = vs.count;
     if (n == 0) {
         hipError_t e = launch_fill_u32(r.weights, (size_t)ntiles, 0u, s, V, vs.ws);
-        if (e == hipSuccess) e = launch_fill_u32(r.status, 1, 0u, s, V, vs.ws);
+        if (e == hipSuccess) e = launch_fill_u32(r.status, 3, 0u, s, V, vs.ws);
         if (e != hipSuccess) return e;
     } else {
         const int sat = (cfg.fb_format == FB_UNORM16 || cfg.fb_format == FB_UNORM8) ? 1 : 0;
@@ -1629,7 +1729,7 @@ using FwdKernel = void (*)(int, const int32_t*, const Rec*, const uint2*, const 
                           const uint32_t*, int, int, int, int, int, const int4*, const int32_t*,
                           float4*, float, float, float, float, float, float, float, int, void*,
                           float*, float*, int32_t*, unsigned long long*, uint32_t*, uint32_t*,
-                          uint64_t);
+                          int, uint64_t);
 
 template <bool TC, bool IN, bool MU>
 static FwdKernel fwd_by_fmt(int rfmt) {
@@ -1667,8 +1767,10 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
     const int rfmt = cfg.fb_round == GS_ROUND_PER_FRAGMENT ? cfg.fb_format : -1;
     const bool tcull = cfg.t_min_fwd > 0.f;
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_cov;
-    // the depth split needs the at-rest state, no T-culling and no per-pixel counters
-    const bool split = r.split && rfmt < 0 && !tcull && !instr;
+    // the saturation exit ends a tile's walk early, so it composites each tile in one item; the
+    // depth split (at-rest state, no T-culling, no counters) serves the full walk
+    const bool freeze = rfmt < 0 && !tcull && !instr && !(cfg.flags & GS_FLAG_COMPOSITE_ALL);
+    const bool split = r.split && rfmt < 0 && !tcull && !instr && !freeze;
     FwdKernel k = V > 1 ? fwd_kernel<true>(rfmt, tcull, instr) : fwd_kernel<false>(rfmt, tcull, instr);
     hipLaunchKernelGGL(k, dim3(split ? ITEMS_PER_TILE * ntiles : ntiles, V), dim3(NT), 0, s, n,
                        n_visible,
@@ -1680,7 +1782,7 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
                        cfg.background[1], cfg.background[2], cfg.fb_format, fb, out_rgb, out_T,
                        out_cov,
                        (stats && (cfg.flags & GS_FLAG_STATS)) ? (unsigned long long*)stats : nullptr,
-                       r.bwd_w, r.status,
+                       r.bwd_w, r.status, freeze ? 1 : 0,
                        vs.ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !split) return e;

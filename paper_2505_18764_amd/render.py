@@ -39,6 +39,7 @@ class RasterConfig:
     sh_degree: int = 3
     stats: bool = False
     background: tuple = (0.0, 0.0, 0.0)   # C += T_final background (zero: Eq. 2 as printed)
+    composite_all: bool = False           # forward: no saturation exit (GS_FLAG_COMPOSITE_ALL)
 
     def c(self, n_views: int = 1) -> L.GsConfig:
         c = L.GsConfig()
@@ -52,7 +53,7 @@ class RasterConfig:
         c.fb_round = L.FB_ROUND[self.fb_round]
         c.reduce_mode = L.REDUCE_MODES[self.reduce_mode]
         c.reduce_threshold = self.reduce_threshold
-        c.flags = 1 if self.stats else 0
+        c.flags = (1 if self.stats else 0) | (4 if self.composite_all else 0)
         for k in range(3):
             c.background[k] = float(self.background[k])
         c.n_views = int(n_views)

@@ -167,8 +167,8 @@ def test_determinism():
 
 
 def test_depth_split_forward():
-    """The forward without counters (the configuration the benchmark times) splits tiles heavier
-    than the mean into depth segments and merges them; a dense centre guarantees splits. Image
+    """The forward without counters and without the saturation exit splits tiles heavier than
+    the mean into depth segments and merges them; a dense centre guarantees splits. Image
     and T against the oracle, and against the unsplit (instrumented) forward; gradients from the
     split forward's framebuffer against the oracle."""
     W, H = 256, 192
@@ -183,7 +183,7 @@ def test_depth_split_forward():
                        depth=g.permutation(np.concatenate([a.depth, b.depth])).astype(np.float32),
                        cov=np.concatenate([a.cov, b.cov]), width=W, height=H)
     G = synth.image_grad(W, H, 29)
-    cfg = R.RasterConfig(reduce_mode="tile")
+    cfg = R.RasterConfig(reduce_mode="tile", composite_all=True)   # no saturation exit
     ws = R.Workspace()
     p = R.prepare_2d(t(s.means2d), t(s.conics), t(s.opacities), t(s.rgb), t(s.depth), W, H, cfg, ws)
     R.raster_setup(p, cfg, ws)
@@ -202,6 +202,43 @@ def test_depth_split_forward():
                     grad=grads9(bw)), ref)
     print("depth split:", e, "covered/px at the centre", ref["cov"][76:116, 104:152].mean())
     assert ref["cov"][76:116, 104:152].mean() > 200
+
+
+def test_saturation_exit_keeps_the_image():
+    """The forward without counters stops a pixel block once no fragment of the view can change
+    its stored colour in FP32 (and T <= 1e-6): on a dense scene (thousands of covered fragments
+    per pixel at its centre) the image must equal, bit for bit, the walk over every covered
+    fragment (the instrumented forward), with T within 1e-6; the walk without the exit (depth
+    split) matches the oracle as before."""
+    W, H = 256, 192
+    g = np.random.default_rng(27)
+    a = synth.splats2d(n=3000, width=W, height=H, seed=27)
+    b = synth.splats2d(n=20000, width=48, height=40, seed=28)
+    b.means2d[:] += np.array([104.0, 76.0], np.float32)
+    s = synth.Splats2D(means2d=np.concatenate([a.means2d, b.means2d]),
+                       conics=np.concatenate([a.conics, b.conics]),
+                       opacities=np.concatenate([a.opacities, b.opacities]),
+                       rgb=np.concatenate([a.rgb, b.rgb]),
+                       depth=g.permutation(np.concatenate([a.depth, b.depth])).astype(np.float32),
+                       cov=np.concatenate([a.cov, b.cov]), width=W, height=H)
+    for fmt in ("f32", "f16"):
+        cfg = R.RasterConfig(fb_format=fmt, reduce_mode="tile")
+        ws = R.Workspace()
+        p = R.prepare_2d(t(s.means2d), t(s.conics), t(s.opacities), t(s.rgb), t(s.depth), W, H,
+                         cfg, ws)
+        R.raster_setup(p, cfg, ws)
+        st = R.new_stats("cuda")
+        fx = R.raster_forward(p, cfg, ws, reuse_setup=True)                      # exit
+        full = R.raster_forward(p, cfg, ws, coverage=True, stats=st, reuse_setup=True)
+        assert R.raster_status(p, cfg, ws) == 0
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(fx["image"].cpu().numpy(), full["image"].cpu().numpy())
+        dT = np.abs(fx["T"].cpu().numpy() - full["T"].cpu().numpy()).max()
+        assert dT <= 1e-6, dT
+        if fmt == "f32":
+            assert (fx["T"].cpu().numpy() >= full["T"].cpu().numpy()).all()   # stopped early
+        print(fmt, "saturation exit: T max-abs vs the full walk", dT,
+              "covered fragments", R.read_stats(st)["fwd_covered"])
 
 
 def test_shared_setup_matches_per_call_setup():
