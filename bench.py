@@ -11,6 +11,7 @@ Prints one JSON line (rank 0). Single GPU only.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -109,7 +110,7 @@ def format_error_table(g, g_ref):
 
 
 # the launches of the timed raster stages (paper mode, FP16 at rest, no counters)
-FWD_KERNELS = ("k_raster_fwd<-1, false, false, false>", "k_raster_merge")
+FWD_KERNELS = ("k_raster_fwd<-1, false, false, false>",)
 BWD_KERNELS = ("k_raster_bwd<-1, false, false, true>",)
 
 
@@ -122,10 +123,10 @@ def main():
     if args.summarize_pmc:
         from paper_2505_18764_amd import pmc
         d = args.summarize_pmc
-        B = ("python -u bench.py --steps 3 --warmup 1 --no-cpu --no-tile --serve-requests 0 "
-             "--no-format-errors --no-views --formats f16")
-        KT = ("python -u bench.py --steps 5 --warmup 1 --no-cpu --no-tile --serve-requests 0 "
-              "--no-format-errors --no-views --formats f16")
+        A = ("python -u bench.py --steps 3 --warmup 1 --no-cpu --no-tile --serve-requests 0 "
+             "--no-format-errors --no-views --no-variants --no-fit --formats f16")
+        B = A + " --no-micro"
+        KT = B.replace("--steps 3", "--steps 5")
         cmd = "\n".join([
             "cd /tmp && export TMPDIR=/tmp && R=<repository root>",
             f"rocprofv3 --pmc FETCH_SIZE --kernel-trace -d $OUT/fetch -o run -- {B.replace('bench.py', '$R/bench.py')}",
@@ -145,6 +146,13 @@ def main():
             pmc.issue_summary(os.path.join(d, "sq"),
                               os.path.join(ROOT, "profiles", "issue_1M_1600x1064_f16.md"), scmd,
                               "1M clustered Gaussians, 1600x1064, FP16 framebuffer")
+        if os.path.isdir(os.path.join(d, "atom")):
+            acmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc " + " ".join(pmc.ATOMIC_COUNTERS)
+                    + f" --kernel-trace -d $OUT/atom -o run -- {A.replace('bench.py', '$R/bench.py')}")
+            pmc.atomic_summary(os.path.join(d, "atom"),
+                               os.path.join(ROOT, "profiles", "atomics_1M_1600x1064_f16.md"), acmd,
+                               "1M clustered Gaussians, 1600x1064, FP16 framebuffer; the FP32 "
+                               "atomic microbenchmark")
         if os.path.isdir(os.path.join(d, "kt")):
             kcmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $OUT/kt "
                     f"-o run -- {KT.replace('bench.py', '$R/bench.py')}")
@@ -196,12 +204,18 @@ def main():
         g2 = R.raster_backward(p, f["fb"], Gd, cfg, ws)
         g3 = R.project_backward(*inp, cam, cfg, g2)
         torch.cuda.synchronize()
-        # fragment counts of this workload (instrumented run, outside the timed region)
+        # fragment counts of this workload (instrumented runs, outside the timed region): the
+        # fragments the timed forward composites (with its saturation exit) and the backward
+        # visits, and every covered fragment (paper mode's full walk, the algorithmic count)
         st = R.new_stats(dev)
         R.raster_forward(p, cfg, ws, fb=f["fb"], image=f["image"], T=f["T"], stats=st)
         R.raster_backward(p, f["fb"], Gd, cfg, ws, stats=st, out=g2)
+        st_all = R.new_stats(dev)
+        cfg_all = dataclasses.replace(cfg, composite_all=True)
+        R.raster_forward(p, cfg_all, ws, fb=f["fb"], image=f["image"], T=f["T"], stats=st_all)
         torch.cuda.synchronize()
         stats = R.read_stats(st)
+        stats["fwd_covered_full_walk"] = R.read_stats(st_all)["fwd_covered"]
         nvis = int(p.n_visible.item())
 
         # every call below runs on torch's current stream, which the events are recorded on; the
@@ -282,7 +296,9 @@ def main():
     head_fmt = "f16" if "f16" in results else list(results)[0]
     head = results[head_fmt]
     st = head["stats"]
-    F, Lv = st["fwd_covered"], st["bwd_live"]
+    # F: fragments the forward composites (its saturation exit stops where no later fragment can
+    # change the stored colour); F_all: every covered fragment (the method's own count)
+    F, F_all, Lv = st["fwd_covered"], st["fwd_covered_full_walk"], st["bwd_live"]
     A = st["bwd_atomic_sets"]
     fwd_ms, bwd_ms = head["stages_ms"]["raster_fwd"], head["stages_ms"]["raster_bwd"]
     S = STATE_BYTES[head_fmt]
@@ -293,7 +309,7 @@ def main():
     # writes the state and reads dL/dC; 36 bytes per atomic set of nine gradients)
     s_T = S // 4
     alg_bytes = {"raster_fwd": F * 2 * S,
-                 "raster_bwd": (F - Lv) * s_T + Lv * (2 * S + 12) + A * 36}
+                 "raster_bwd": (F_all - Lv) * s_T + Lv * (2 * S + 12) + A * 36}
     roof = {}
     for name, ms, flops, keys in (("raster_fwd", fwd_ms, F * FLOP_FWD_PER_COVERED, FWD_KERNELS),
                                   ("raster_bwd", bwd_ms, Lv * FLOP_BWD_PER_LIVE, BWD_KERNELS)):
@@ -371,8 +387,10 @@ def main():
                         "stages_ms": {s: round(x, 4) for s, x in v["stages_ms"].items()},
                         "wall_ms_per_view": round(v["wall_ms_per_view"], 4)}
                     for k, v in results.items()},
-        "fragments": {"covered": F, "live": Lv, "n_visible": head["n_visible"],
-                      "covered_per_s": round(F / (fwd_ms * 1e-3), 1),
+        "fragments": {"covered": F_all, "composited": F, "live": Lv,
+                      "n_visible": head["n_visible"],
+                      "covered_per_s": round(F_all / (fwd_ms * 1e-3), 1),
+                      "composited_per_s": round(F / (fwd_ms * 1e-3), 1),
                       "live_per_s": round(Lv / (bwd_ms * 1e-3), 1),
                       "atomic_rate": round(A / max(1, Lv), 5),
                       "cohesion": round(st["bwd_cohesive"] / max(1, st["bwd_wave_reductions"] +
@@ -735,6 +753,7 @@ def cpu_full(args):
     G1 = synth.image_grad(c1["width"], c1["height"], 31)
     out["cfg1_full_s"] = {str(k): round(_oracle_full_2d(s1, c1["width"], c1["height"], G1, k), 4)
                           for k in (nth, 1)}
+    print(json.dumps({"cfg1_full_s": out["cfg1_full_s"]}), flush=True)
     c2 = synth.CFG2
     sc2 = synth.scene3d(c2["n"], seed=c2["seed"])
     cam2 = synth.camera_front(c2["width"], c2["height"], c2["fx"])
@@ -744,9 +763,12 @@ def cpu_full(args):
         cfg = oracle.OracleConfig(nthreads=k)
         t0 = time.perf_counter()
         r = oracle.render_scene(sc2, cam2, dL_dimg=G2, cfg=cfg)
+        t_fwd = time.perf_counter() - t0
+        print(json.dumps({"cfg2_threads": k, "render_s": round(t_fwd, 2)}), flush=True)
+        t0 = time.perf_counter()
         og = r["grad"]
         oracle.preprocess_vjp(sc2, cam2, og[:, 0:2], og[:, 2:5], og[:, 6:9], og[:, 5], cfg)
-        out["cfg2_full_s"][str(k)] = round(time.perf_counter() - t0, 2)
+        out["cfg2_full_s"][str(k)] = round(t_fwd + time.perf_counter() - t0, 2)
         print(json.dumps({"cfg2_threads": k, "s": out["cfg2_full_s"][str(k)]}), flush=True)
     c3 = synth.CFG3
     sc3 = synth.scene3d(c3["n"], seed=c3["seed"])
@@ -756,6 +778,9 @@ def cpu_full(args):
     for k, blocks in ((nth, 96), (1, 24)):
         tot, d = _oracle_view_sample(sc3, cam3, G3, blocks, k)
         out["cfg3_sampled_ms_per_view"][str(k)] = {"ms": round(tot * 1e3, 1), "blocks": blocks}
+        print(json.dumps({"cfg3_threads": k, **out["cfg3_sampled_ms_per_view"][str(k)]}), flush=True)
     print(json.dumps(out), flush=True)
+
+
 if __name__ == "__main__":
     main()

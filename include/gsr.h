@@ -298,7 +298,8 @@ int gs_raster_setup(const gs_camera* cam, const gs_config* cfg, int32_t n,
  * pixel block stops compositing once each of its pixels has T <= 1e-6 and, in FP32, no fragment
  * of the view can change its colour any more (C_ch + 2 T max|c| == C_ch): the stored colour is
  * then bit-identical to compositing every fragment, and T within 1e-6 of its product over all
- * of them. With counters (stats, out_coverage) every covered fragment is composited and counted.
+ * of them. With out_coverage every covered fragment is composited and counted; stats count the
+ * fragments actually composited (with the exit unless GS_FLAG_COMPOSITE_ALL is set).
  * In the unorm formats splat colours saturate to 1 (Sec. 3.3).
  * Inputs [n] by splat id: means2d [n,2], conics [n,3], opacities [n], rgb [n,3];
  *   sorted_ids [n] (a permutation of 0..n-1, as gs_sort leaves it), n_visible [1] device int32.

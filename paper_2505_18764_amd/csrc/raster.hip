@@ -746,7 +746,8 @@ struct Half32 {
 // fragment adds T alpha c with |T alpha c| <= T c_max, which rounds to C under that condition
 // (rounding is monotone in the addend), so C is bit-identical to compositing every covered
 // fragment and T is within 1e-6 of its final value. The walk of a tile ends when all its
-// sub-blocks are done. The instances with counters walk every fragment (exact coverage counts).
+// sub-blocks are done. A call that asks for per-pixel coverage walks every fragment (exact
+// counts); one that only counts statistics counts the fragments the exit composites.
 template <int RFMT, bool TCULL, bool INSTR, bool MULTI>
 __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     int n, const int32_t* __restrict__ nvis_ptr, const Rec* __restrict__ rec,
@@ -760,7 +761,7 @@ __global__ __launch_bounds__(NT, 7) void k_raster_fwd(
     uint32_t* __restrict__ bwd_w, uint32_t* __restrict__ status, int freeze_on, uint64_t vws) {
     __shared__ Walk<ROUND_CHUNKS> w;
     status = view_bytes(status, vws);
-    constexpr bool FREEZE = RFMT < 0 && !TCULL && !INSTR;
+    constexpr bool FREEZE = RFMT < 0 && !TCULL;
     constexpr bool ALIVE = TCULL || FREEZE;        // sub-blocks can drop out of the walk
     const bool freeze = FREEZE && freeze_on;
     const float cm2 = freeze ? 2.f * __uint_as_float(status[2]) : 0.f;
@@ -1769,7 +1770,7 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
     const bool instr = (stats && (cfg.flags & GS_FLAG_STATS)) || out_cov;
     // the saturation exit ends a tile's walk early, so it composites each tile in one item; the
     // depth split (at-rest state, no T-culling, no counters) serves the full walk
-    const bool freeze = rfmt < 0 && !tcull && !instr && !(cfg.flags & GS_FLAG_COMPOSITE_ALL);
+    const bool freeze = rfmt < 0 && !tcull && !out_cov && !(cfg.flags & GS_FLAG_COMPOSITE_ALL);
     const bool split = r.split && rfmt < 0 && !tcull && !instr && !freeze;
     FwdKernel k = V > 1 ? fwd_kernel<true>(rfmt, tcull, instr) : fwd_kernel<false>(rfmt, tcull, instr);
     hipLaunchKernelGGL(k, dim3(split ? ITEMS_PER_TILE * ntiles : ntiles, V), dim3(NT), 0, s, n,

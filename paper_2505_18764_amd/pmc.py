@@ -193,3 +193,41 @@ def issue_summary(path: str, out_md: str, command: str, workload: str, top: int 
     with open(os.path.join(os.path.dirname(out_md), "issue.json"), "w") as fh:
         json.dump(js, fh, indent=1)
     return res
+
+
+# L2-side and L1-side atomic request counters (summed over the L2 channels / L1 instances): the
+# requests the L2 executes, those it forwards to memory, and the vector-L1 requests with and
+# without a returned value.
+ATOMIC_COUNTERS = ("TCC_ATOMIC_sum", "TCC_EA0_ATOMIC_sum", "TCP_TCC_ATOMIC_WITH_RET_REQ_sum",
+                   "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum")
+
+
+def atomic_summary(path: str, out_md: str, command: str, workload: str, top: int = 10) -> dict:
+    """Per kernel that issues atomics: the counters of ATOMIC_COUNTERS per launch and the L2
+    atomic rate (TCC_ATOMIC per second of launch time)."""
+    m = counter_means(path)
+    res = {}
+    lines = [f"# Atomic requests per launch: {workload}", "",
+             "Command (on one MI355X; `$R` is the repository root, `$OUT` any scratch directory):",
+             "", "```", command, "```", "",
+             "| kernel | calls | mean us | L2 atomics (M) | to memory (M) | L1 req. with return (M) "
+             "| L1 req. without return (M) | L2 atomics / s (G) |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    rows = [k for k in m if m[k].get("TCC_ATOMIC_sum", 0) > 0]
+    for k in sorted(rows, key=lambda k: -m[k]["_dur_ns"] * m[k]["_calls"])[:top]:
+        v = m[k]
+        rate = v["TCC_ATOMIC_sum"] / (v["_dur_ns"] * 1e-9)
+        res[k] = {c: v.get(c) for c in ATOMIC_COUNTERS}
+        res[k].update(mean_ns=v["_dur_ns"], calls=v["_calls"], l2_atomics_per_s=rate)
+        cells = [f"{v.get(c, 0) / 1e6:.2f}" for c in ATOMIC_COUNTERS]
+        lines.append(f"| `{k}` | {v['_calls']} | {v['_dur_ns'] / 1e3:.1f} | " + " | ".join(cells)
+                     + f" | {rate / 1e9:.1f} |")
+    h = source_hash()
+    lines += ["", f"Source hash of the kernels measured: `{h}`."]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    js = {k: dict(v, source_hash=h) for k, v in res.items()}
+    js["_command"] = command
+    with open(os.path.join(os.path.dirname(out_md), "atomics.json"), "w") as fh:
+        json.dump(js, fh, indent=1)
+    return res

@@ -61,7 +61,7 @@ def test_full_size_crop_and_samples(view, fmt):
     R.raster_backward(p, fi["fb"], t(G), cfg, ws, stats=st, reuse_setup=True)
     torch.cuda.synchronize()
     img = f["image"].cpu().numpy()
-    # the split forward agrees with one pass per tile to FP32 reassociation
+    # the uninstrumented forward agrees with the instrumented one (both take the saturation exit)
     assert np.abs(img - fi["image"].cpu().numpy()).max() <= (2e-6 if fmt == "f32" else 1e-3)
     ref = oracle.raster(arr["means2d"], arr["conics"], arr["opacities"], arr["rgb"], order, W, H,
                         crop=crop, dL_dimg=G, cfg=ocfg)

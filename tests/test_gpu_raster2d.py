@@ -230,15 +230,20 @@ def test_saturation_exit_keeps_the_image():
         st = R.new_stats("cuda")
         fx = R.raster_forward(p, cfg, ws, reuse_setup=True)                      # exit
         full = R.raster_forward(p, cfg, ws, coverage=True, stats=st, reuse_setup=True)
+        sx = R.new_stats("cuda")        # statistics only: counts the fragments the exit composites
+        fc = R.raster_forward(p, cfg, ws, stats=sx, reuse_setup=True)
         assert R.raster_status(p, cfg, ws) == 0
         torch.cuda.synchronize()
         np.testing.assert_array_equal(fx["image"].cpu().numpy(), full["image"].cpu().numpy())
+        np.testing.assert_array_equal(fx["image"].cpu().numpy(), fc["image"].cpu().numpy())
+        n_all, n_ex = R.read_stats(st)["fwd_covered"], R.read_stats(sx)["fwd_covered"]
+        assert 0 < n_ex < n_all, (n_ex, n_all)
         dT = np.abs(fx["T"].cpu().numpy() - full["T"].cpu().numpy()).max()
         assert dT <= 1e-6, dT
         if fmt == "f32":
             assert (fx["T"].cpu().numpy() >= full["T"].cpu().numpy()).all()   # stopped early
         print(fmt, "saturation exit: T max-abs vs the full walk", dT,
-              "covered fragments", R.read_stats(st)["fwd_covered"])
+              "covered fragments", n_all, "composited", n_ex)
 
 
 def test_shared_setup_matches_per_call_setup():
