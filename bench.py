@@ -94,7 +94,7 @@ def _traffic(kernels):
 
 
 def format_error_table(g, g_ref):
-    """The paper's mixed-precision error measure (Sec. 4, Table 3): RMSE of all gradient
+    """The paper's mixed-precision error measure (Sec. 4.6, Table 4): RMSE of all gradient
     elements against the FP32 path, and the mean relative error |g - g_ref| / |g_ref| over the
     elements whose reference magnitude lies in [10, inf), [0.1, 10) and [1e-3, 0.1)."""
     g = np.asarray(g, np.float64).reshape(-1)
@@ -108,6 +108,9 @@ def format_error_table(g, g_ref):
         out["n_" + name[4:]] = int(m.sum())
     return out
 
+
+# consecutive lanes whose FP32 atomic adds reach the L2 as one request (a 64-byte line)
+LANES_PER_ATOMIC_REQUEST = 16
 
 # the launches of the timed raster stages (paper mode, FP16 at rest, no counters)
 FWD_KERNELS = ("k_raster_fwd<-1, false, false, false>",)
@@ -332,17 +335,29 @@ def main():
             r["hbm_copy_gbs_measured"] = micro["copy_gbs"]
         roof[name] = r
     if micro:
-        # the backward's atomics against the measured FP32-atomic throughput: each set adds
-        # nine values, first with a returning add, then (when its rounding error is not zero)
-        # a second add of that error
+        # the backward's atomics against the measured FP32-atomic throughput. By adds: each set
+        # adds nine values, first with a returning add, then (when its rounding error is not
+        # zero) a second add of that error. By requests: 16 consecutive lanes' adds travel as one
+        # 64-byte request (the microbenchmark's counters: 67.1M adds, 4.19M L2 requests), and the
+        # kernel's own request counts come from the committed counter profile.
         n_at = 9 * A
-        t_ret = n_at / micro["atomic_per_s"]["spread_return"]
-        t_plain = n_at / micro["atomic_per_s"]["spread"]
-        roof["raster_bwd"]["atomics"] = {
-            "sets": A, "returning_adds": n_at, "error_adds_at_most": n_at,
-            "bound_ms": round((t_ret + t_plain) * 1e3, 4),
-            "frac_of_kernel_time": round((t_ret + t_plain) * 1e3 / bwd_ms, 4),
-            "rate_per_s_measured": micro["atomic_per_s"]}
+        rate = micro["atomic_per_s"]
+        t_ret = n_at / rate["spread_return"]
+        t_plain = n_at / rate["spread"]
+        at = {"sets": A, "returning_adds": n_at, "error_adds_at_most": n_at,
+              "bound_ms_by_adds": round((t_ret + t_plain) * 1e3, 4),
+              "rate_per_s_measured": rate, "lanes_per_request": LANES_PER_ATOMIC_REQUEST}
+        req_ret = _profile("atomics.json", BWD_KERNELS, "TCP_TCC_ATOMIC_WITH_RET_REQ_sum")
+        req_plain = _profile("atomics.json", BWD_KERNELS, "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum")
+        if req_ret is not None and req_plain is not None:
+            t_req = (req_ret / (rate["spread_return"] / LANES_PER_ATOMIC_REQUEST) +
+                     req_plain / (rate["spread"] / LANES_PER_ATOMIC_REQUEST))
+            at.update(requests_with_return=round(req_ret), requests_without_return=round(req_plain),
+                      bound_ms_by_requests=round(t_req * 1e3, 4),
+                      frac_of_kernel_time=round(t_req * 1e3 / bwd_ms, 4))
+        else:
+            at["frac_of_kernel_time"] = round((t_ret + t_plain) * 1e3 / bwd_ms, 4)
+        roof["raster_bwd"]["atomics"] = at
     dom = "raster_fwd" if fwd_ms >= bwd_ms else "raster_bwd"
 
     extra = {}

@@ -17,28 +17,30 @@ __global__ __launch_bounds__(256) void k_micro_copy(const uint4* __restrict__ sr
 
 // per x GS_MICRO_THREADS FP32 atomic adds into slots[0 .. nslots) (nslots a power of two), each
 // thread `per` of them:
-//   mode 0 (GS_MICRO_ATOMIC_SPREAD): add k of thread t goes to slot (t + k T) mod nslots with T
+//   MODE 0 (GS_MICRO_ATOMIC_SPREAD): add k of thread t goes to slot (t + k T) mod nslots with T
 //     the thread count: consecutive lanes hit consecutive words, as the tile flush's slot-by-slot
-//     adds do, and the address walks the whole buffer;
-//   mode 1 (GS_MICRO_ATOMIC_SPREAD_RETURN): the same with the old value returned and consumed,
+//     adds do, and the address walks the whole buffer; the old value is not returned;
+//   MODE 1 (GS_MICRO_ATOMIC_SPREAD_RETURN): the same with the old value returned and consumed,
 //     as the compensated flush's first add;
-//   mode 2 (GS_MICRO_ATOMIC_WAVE_SAME): all lanes of a wave add to one word per instruction (the
+//   MODE 2 (GS_MICRO_ATOMIC_WAVE_SAME): all lanes of a wave add to one word per instruction (the
 //     per-fragment atomics of the naive reduction when one splat covers the wave).
+// One instance per mode, so that each compiles to its own form of the atomic (with one kernel,
+// the returning form served both the returning and the non-returning mode).
 // The values added are exact in FP32 (1/64), so the slots' sums are checkable.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_micro_atomic(float* __restrict__ slots, uint32_t mask,
-                                                      int per, int mode,
-                                                      float* __restrict__ sink) {
+                                                      int per, float* __restrict__ sink) {
     const uint32_t T = gridDim.x * blockDim.x;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     float acc = 0.f;
     for (int k = 0; k < per; ++k) {
         uint32_t i;
-        if (mode == 2) i = ((t >> 6) + (uint32_t)k * (T >> 6)) & mask;
+        if constexpr (MODE == 2) i = ((t >> 6) + (uint32_t)k * (T >> 6)) & mask;
         else i = (t + (uint32_t)k * T) & mask;
-        if (mode == 1) acc += unsafeAtomicAdd(slots + i, 1.0f / 64.0f);
+        if constexpr (MODE == 1) acc += unsafeAtomicAdd(slots + i, 1.0f / 64.0f);
         else unsafeAtomicAdd(slots + i, 1.0f / 64.0f);
     }
-    if (mode == 1 && acc == -1.0f) sink[0] = acc;      // keeps the returned values live
+    if (MODE == 1 && acc == -1.0f) sink[0] = acc;      // keeps the returned values live
 }
 
 hipError_t launch_micro_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
@@ -52,8 +54,11 @@ hipError_t launch_micro_copy(const void* src, void* dst, size_t bytes, hipStream
 
 hipError_t launch_micro_atomic(float* slots, size_t nslots, int per, int mode, hipStream_t s) {
     if (per == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_micro_atomic, dim3(GS_MICRO_THREADS / 256), dim3(256), 0, s, slots,
-                       (uint32_t)(nslots - 1), per, mode, slots);
+    const dim3 g(GS_MICRO_THREADS / 256), b(256);
+    const uint32_t mask = (uint32_t)(nslots - 1);
+    if (mode == 0) hipLaunchKernelGGL(k_micro_atomic<0>, g, b, 0, s, slots, mask, per, slots);
+    else if (mode == 1) hipLaunchKernelGGL(k_micro_atomic<1>, g, b, 0, s, slots, mask, per, slots);
+    else hipLaunchKernelGGL(k_micro_atomic<2>, g, b, 0, s, slots, mask, per, slots);
     return hipGetLastError();
 }
 

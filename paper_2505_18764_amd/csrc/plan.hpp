@@ -31,9 +31,11 @@ constexpr int ITEMS_PER_TILE = SEG_DIV + 1;
 __host__ __device__ inline float bucket_scale(uint32_t wmax) {
     return (float)NBUCKETS / ((float)wmax + 1.0f);
 }
+// The clamp happens in FP32, before the conversion, so a weight above wmax lands in bucket 0
+// on any target (an out-of-range float-to-int conversion is undefined on the host).
 __host__ __device__ inline int weight_bucket(uint32_t x, float scale) {
-    const int b = (int)((float)x * scale);
-    return NBUCKETS - 1 - (b < NBUCKETS - 1 ? b : NBUCKETS - 1);
+    const float f = (float)x * scale;
+    return NBUCKETS - 1 - (f < (float)(NBUCKETS - 1) ? (int)f : NBUCKETS - 1);
 }
 
 // out[0 .. count) = the indices 0 .. count-1 ordered by bucket (heaviest first, any order inside

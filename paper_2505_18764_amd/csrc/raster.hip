@@ -1194,6 +1194,9 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     // read-only dL/dC and, for a loss on the final transmittance, gTT = dL/dT_final T_final
     // (T_final = prod (1 - alpha_j) contributes -gTT / (1 - alpha_i) to dL/dalpha_i).
     float px[4], py[4], Cp[4][3], T[4], G[4][3], gTT[4];
+    // The tile instance with the state at rest carries only D = dL/dC . C' + gTT per pixel:
+    // Eq. 7 needs C' only through that dot product, and Eqs. 5-6 update it as D -= w (dL/dC . c).
+    float D[4];
     float gbg[3] = {0.f, 0.f, 0.f};     // this lane's share of dL/dbackground = sum dL/dC T_final
     bool valid[4];
     uint32_t nlive[4];
@@ -1209,12 +1212,14 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
         Cp[s][0] = Cp[s][1] = Cp[s][2] = 0.f;
         G[s][0] = G[s][1] = G[s][2] = 0.f;
         gTT[s] = 0.f;
+        D[s] = 0.f;
         if (valid[s]) {
             const size_t i = (size_t)Y * W + X;
             const float4 v = fb_load(fb, fb_fmt, i);
             Cp[s][0] = v.x; Cp[s][1] = v.y; Cp[s][2] = v.z;
             G[s][0] = dL_dimg[i]; G[s][1] = dL_dimg[P + i]; G[s][2] = dL_dimg[2 * P + i];
             if (dL_dT) gTT[s] = dL_dT[i] * v.w;
+            D[s] = fmaf(G[s][2], v.z, fmaf(G[s][1], v.y, fmaf(G[s][0], v.x, gTT[s])));
             gbg[0] = fmaf(G[s][0], v.w, gbg[0]);
             gbg[1] = fmaf(G[s][1], v.w, gbg[1]);
             gbg[2] = fmaf(G[s][2], v.w, gbg[2]);
@@ -1225,6 +1230,12 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
     nvis = nvis < 0 ? 0 : (nvis > n ? n : nvis);
     BwdCounts cnt = {0, 0, 0, 0, 0, 0};
     uint32_t nq = 0;
+    // tile_scale: the factors the tile instance at rest leaves out of its per-fragment sums, for
+    // the totals that row r's first lane holds after wave_sum9 (gradients j0 and j0 + 4 with
+    // j0 = 0, 2, 1, 3 for r = 0..3; gradient 5, row 2's, takes the entry's 1/o)
+    const int lrow = lane >> 4;
+    const float sa = lrow == 1 ? -0.5f : (lrow == 3 ? -1.f : -2.f * (1.0f / LOG2E));
+    const float sb = lrow == 0 ? -0.5f : 1.f;
     const bool lane_acc = TILEM || (mode == GS_REDUCE_HYBRID_LANE || mode == GS_REDUCE_TILE);
 
     const uint32_t* trow = wpr > 0 ? bits + (size_t)tile * wpr : nullptr;
@@ -1295,37 +1306,63 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                                 acc[6] = fmaf(G[s][0], wt, acc[6]);
                                 acc[7] = fmaf(G[s][1], wt, acc[7]);
                                 acc[8] = fmaf(G[s][2], wt, acc[8]);
-                                // Eq. 7, and the final transmittance's share
-                                const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) +
-                                                  G[s][1] * (cg * Ti - Cp[s][1]) +
-                                                  G[s][2] * (cb * Ti - Cp[s][2]) - gTT[s]) *
-                                                 __builtin_amdgcn_rcpf(1.f - al);
-                                // Eqs. 5, 6
-                                Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
-                                Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
-                                Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
-                                if constexpr (RFMT == FB_F16) T[s] = fmaf(-Ti, alm, Ti);
-                                else T[s] = Ti - wt;
-                                if constexpr (RFMT >= 0) {   // idempotent on unchanged lanes
-                                    Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
-                                    Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
-                                    Cp[s][2] = fb_round<RFMT>(Cp[s][2]);
-                                    T[s] = fb_round<RFMT>(T[s]);
+                                if constexpr (RFMT < 0) {
+                                    // Eq. 7 as dL/dC . c T - D, and Eqs. 5-6 applied to D
+                                    const float gc =
+                                        fmaf(G[s][2], cb, fmaf(G[s][1], cg, G[s][0] * cr));
+                                    const float ga = fmaf(gc, Ti, -D[s]) *
+                                                     __builtin_amdgcn_rcpf(1.f - al);
+                                    D[s] = fmaf(-wt, gc, D[s]);
+                                    T[s] = Ti - wt;
+                                    // h = dL/dalpha alpha (zero through a clamped alpha); the
+                                    // sums below leave out factors that are the same for every
+                                    // fragment of the entry: dL/do = (1/o) sum h; dL/dq =
+                                    // -1/2 h, so the conic sums carry -1/2 (the cross term -1)
+                                    // and the mean sums -2 / log2(e) (the pre-scaled factors).
+                                    // They are applied to the wave's totals (tile_scale).
+                                    const float h = (live && araw < amax) ? ga * araw : 0.f;
+                                    acc[5] += h;
+                                    const float gy = fmaf(A.w, au, B.x * dy);
+                                    acc[0] = fmaf(h, au, acc[0]);
+                                    acc[1] = fmaf(h, gy, acc[1]);
+                                    const float hdx = h * dx;
+                                    acc[2] = fmaf(hdx, dx, acc[2]);
+                                    acc[3] = fmaf(hdx, dy, acc[3]);
+                                    acc[4] = fmaf(h * dy, dy, acc[4]);
+                                } else {
+                                    // Eq. 7, and the final transmittance's share
+                                    const float ga = (G[s][0] * (cr * Ti - Cp[s][0]) +
+                                                      G[s][1] * (cg * Ti - Cp[s][1]) +
+                                                      G[s][2] * (cb * Ti - Cp[s][2]) - gTT[s]) *
+                                                     __builtin_amdgcn_rcpf(1.f - al);
+                                    // Eqs. 5, 6
+                                    Cp[s][0] = fmaf(-wt, cr, Cp[s][0]);
+                                    Cp[s][1] = fmaf(-wt, cg, Cp[s][1]);
+                                    Cp[s][2] = fmaf(-wt, cb, Cp[s][2]);
+                                    if constexpr (RFMT == FB_F16) T[s] = fmaf(-Ti, alm, Ti);
+                                    else T[s] = Ti - wt;
+                                    if constexpr (RFMT >= 0) {   // idempotent on unchanged lanes
+                                        Cp[s][0] = fb_round<RFMT>(Cp[s][0]);
+                                        Cp[s][1] = fb_round<RFMT>(Cp[s][1]);
+                                        Cp[s][2] = fb_round<RFMT>(Cp[s][2]);
+                                        T[s] = fb_round<RFMT>(T[s]);
+                                    }
+                                    // bwd_diff (zero through a clamped alpha), as in the paper
+                                    // modes: h = dL/dalpha alpha; dalpha/do = exp(-q/2);
+                                    // dL/dq = -h / 2; dp/dd in the factored form
+                                    // (a' u, k a' u + d' dy)
+                                    const float h = (live && araw < amax) ? ga * araw : 0.f;
+                                    acc[5] = fmaf(h, inv_o, acc[5]);
+                                    const float gq = -0.5f * h;
+                                    const float gm = -2.f * (h * (1.0f / LOG2E));
+                                    const float gy = fmaf(A.w, au, B.x * dy);
+                                    acc[0] = fmaf(gm, au, acc[0]);
+                                    acc[1] = fmaf(gm, gy, acc[1]);
+                                    const float gdx = gq * dx;
+                                    acc[2] = fmaf(gdx, dx, acc[2]);
+                                    acc[3] = fmaf(2.f * gdx, dy, acc[3]);
+                                    acc[4] = fmaf(gq * dy, dy, acc[4]);
                                 }
-                                // bwd_diff (zero through a clamped alpha), as in the paper modes:
-                                // h = dL/dalpha alpha; dalpha/do = exp(-q/2); dL/dq = -h / 2;
-                                // dp/dd in the factored form (a' u, k a' u + d' dy)
-                                const float h = (live && araw < amax) ? ga * araw : 0.f;
-                                acc[5] = fmaf(h, inv_o, acc[5]);
-                                const float gq = -0.5f * h;
-                                const float gm = -2.f * (h * (1.0f / LOG2E));
-                                const float gy = fmaf(A.w, au, B.x * dy);
-                                acc[0] = fmaf(gm, au, acc[0]);
-                                acc[1] = fmaf(gm, gy, acc[1]);
-                                const float gdx = gq * dx;
-                                acc[2] = fmaf(gdx, dx, acc[2]);
-                                acc[3] = fmaf(2.f * gdx, dy, acc[3]);
-                                acc[4] = fmaf(gq * dy, dy, acc[4]);
                             }
                             if (INSTR) {
                                 cnt.evaluated += valid[s];
@@ -1432,6 +1469,10 @@ __global__ __launch_bounds__(NT, TILEM ? 5 : 1) void k_raster_bwd(
                             wave_sum9(acc, ra, rb, rc);
                             if ((lane & 15) == 0) {
                                 const int row = lane >> 4, j0 = ((row & 1) << 1) | (row >> 1);
+                                if constexpr (TILEM && RFMT < 0) {   // tile_scale
+                                    ra *= sa;
+                                    rb *= row == 2 ? inv_o : sb;
+                                }
                                 atomicAdd(tg + k * 9 + j0, ra);
                                 atomicAdd(tg + k * 9 + j0 + 4, rb);
                                 if (row == 0) atomicAdd(tg + k * 9 + 8, rc);

@@ -202,10 +202,31 @@ ATOMIC_COUNTERS = ("TCC_ATOMIC_sum", "TCC_EA0_ATOMIC_sum", "TCP_TCC_ATOMIC_WITH_
                    "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum")
 
 
+def _longest_dispatches(path: str, prefix: str) -> dict:
+    """{kernel: {counter: value, '_calls': 1, '_dur_ns': duration}} for the longest dispatch of
+    each kernel whose name starts with `prefix` (a microbenchmark's measured launch, not its
+    warm-up)."""
+    cur = sqlite3.connect(_db(path)).cursor()
+    per = collections.defaultdict(lambda: collections.defaultdict(dict))
+    for k, c, v, d, du in cur.execute(
+            "select kernel_name, counter_name, value, dispatch_id, duration from counters_collection"):
+        k = short_name(k)
+        if k.startswith(prefix):
+            per[k][d][c] = per[k][d].get(c, 0.0) + float(v)
+            per[k][d]["_dur_ns"] = float(du)
+    out = {}
+    for k, ds in per.items():
+        best = max(ds.values(), key=lambda e: e["_dur_ns"])
+        out[k] = dict(best, _calls=1)
+    return out
+
+
 def atomic_summary(path: str, out_md: str, command: str, workload: str, top: int = 10) -> dict:
     """Per kernel that issues atomics: the counters of ATOMIC_COUNTERS per launch and the L2
-    atomic rate (TCC_ATOMIC per second of launch time)."""
+    atomic rate (TCC_ATOMIC per second of launch time); for the atomic microbenchmark, its
+    measured launch (the longest) rather than the mean with its warm-up."""
     m = counter_means(path)
+    m.update(_longest_dispatches(path, "k_micro_atomic"))
     res = {}
     lines = [f"# Atomic requests per launch: {workload}", "",
              "Command (on one MI355X; `$R` is the repository root, `$OUT` any scratch directory):",

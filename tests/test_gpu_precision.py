@@ -1,7 +1,7 @@
 """The precision sweep at the benchmark view (1M clustered Gaussians, 1600x1064): each framebuffer
 format (FP32, FP16, unorm16, BF16) against the FP64 oracle on four 256x256 crops, the centre crop
 (672, 404) and three 8-aligned crops drawn with seed 33 (Sec. 3.3, mixed-precision rendering;
-Table 3 measures the same formats). Both sides read the oracle's FP64 projection rounded to FP32,
+Table 4 measures the same formats). Both sides read the oracle's FP64 projection rounded to FP32,
 so the error is the raster's: the loss is supported on the crop (dL/dC ~ U[-1, 1] there, zero
 elsewhere and at pixels with a borderline oracle decision, R19), and the gradients of all splats
 w.r.t. (mean2d, conic, opacity, rgb) are compared per parameter group and over all.

@@ -88,6 +88,11 @@ def test_bucket_order_pads_and_tolerates_a_small_wmax(plan):
     # a bound below some weights still gives a permutation (those weights share bucket 0)
     out = _order(plan, w, wmax=10)
     np.testing.assert_array_equal(np.sort(out), np.arange(3000))
+    # weights whose scaled value leaves the int range (a zero bound, weights near 2^32)
+    w2 = np.array([2**32 - 1, 2**31, 5, 0, 2**32 - 1], np.uint32)
+    for wmax in (0, 1, 2**20):
+        out = _order(plan, w2, wmax=wmax)
+        np.testing.assert_array_equal(np.sort(out), np.arange(5))
     out = _order(plan, np.zeros(0, np.uint32), pad=16)   # no items at all
     assert (out == -1).all()
 
