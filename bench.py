@@ -156,14 +156,23 @@ def main():
                                os.path.join(ROOT, "profiles", "atomics_1M_1600x1064_f16.md"), acmd,
                                "1M clustered Gaussians, 1600x1064, FP16 framebuffer; the FP32 "
                                "atomic microbenchmark")
+        if os.path.isdir(os.path.join(d, "stall1")) and os.path.isdir(os.path.join(d, "stall2")):
+            cmds = [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {' '.join(c)} --kernel-trace "
+                    f"-d $OUT/stall{i + 1} -o run -- {B.replace('bench.py', '$R/bench.py')}"
+                    for i, c in enumerate(pmc.STALL_COUNTERS)]
+            pmc.stall_summary([os.path.join(d, "stall1"), os.path.join(d, "stall2")],
+                              os.path.join(ROOT, "profiles", "stalls_1M_1600x1064_f16.md"), cmds,
+                              "1M clustered Gaussians, 1600x1064, FP16 framebuffer")
         if os.path.isdir(os.path.join(d, "kt")):
             kcmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d $OUT/kt "
                     f"-o run -- {KT.replace('bench.py', '$R/bench.py')}")
             pmc.trace_summary(os.path.join(d, "kt"),
                               os.path.join(ROOT, "profiles", "kernels_1M_1600x1064_f16.md"), kcmd,
                               "1M clustered Gaussians, 1600x1064, FP16 framebuffer",
-                              note="Seven views: one warmup, one instrumented (the INSTR = true "
-                                   "instances count fragments for the stats), five timed.")
+                              note="Six views: one warm-up, one instrumented (the INSTR = true "
+                                   "instances count fragments: a forward with the saturation "
+                                   "exit, a forward of every covered fragment and a backward), "
+                                   "five timed (the timed loop's views and the stage timings).")
         return
     if args.cpu_full:
         cpu_full(args)

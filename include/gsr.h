@@ -382,7 +382,9 @@ int gs_raster_status(const gs_config* cfg, int32_t n, int32_t width, int32_t hei
  *                            partial slot or -1); n_items [V] int64 the item count.
  * Each pointer may be NULL. The item arrays exist only when the workspace holds a depth split
  * (GS_ERR_UNSUPPORTED if item_order, items or n_items is requested without one: images of more
- * than 4096 tiles). A setup (or forward) must have run on the workspace first.
+ * than 4096 tiles), and are planned by the forward that splits (GS_FLAG_COMPOSITE_ALL with the
+ * state at rest, no forward T-cull and no counters): after other calls they hold what the last
+ * such forward planned, or nothing. A setup (or forward) must have run on the workspace first.
  */
 int gs_raster_debug_schedule(const gs_config* cfg, int32_t n, int32_t width, int32_t height,
                              const void* ws, size_t ws_bytes, int32_t* fwd_order,

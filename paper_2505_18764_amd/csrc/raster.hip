@@ -1672,8 +1672,8 @@ RasterWs carve_raster_ws(void* ws, int n, int width, int height, bool bwd) {
     return r;
 }
 
-// Records, tile rectangles, tile weights, the occupancy bitmap and the schedule (tile order and,
-// where the workspace allows it, the depth-split work items).
+// Records, tile rectangles, tile weights, the occupancy bitmap and the schedule (tile order, the
+// column and segment counts from which a forward that splits tiles plans its work items).
 static hipError_t raster_setup(const gs_config& cfg, int width, int height, int n,
                                const int32_t* sorted_ids, const int32_t* n_visible,
                                const float* means2d, const float* conics, const float* opac,
@@ -1700,15 +1700,20 @@ static hipError_t raster_setup(const gs_config& cfg, int width, int height, int 
     }
     hipLaunchKernelGGL(k_plan_tiles, dim3(1, V), dim3(NBUCKETS), 0, s, r.weights, ntiles, r.order,
                        r.split, r.tile_k, r.tile_first, r.counters, r.bwd_w, vs.ws);
-    if (r.split) {
-        hipLaunchKernelGGL(k_plan_cuts, dim3(ntiles, V), dim3(64), 0, s, r.weights,
-                           (const uint16_t*)r.colcnt, r.wpr / COL_WORDS, ntiles,
-                           (const int32_t*)r.tile_k,
-                           (const int32_t*)r.tile_first, r.items, r.item_w, vs.ws);
-        hipLaunchKernelGGL(k_plan_items, dim3(1, V), dim3(NBUCKETS), 0, s,
-                           (const uint32_t*)r.item_w, ntiles, (const unsigned long long*)r.counters,
-                           r.item_order, vs.ws);
-    }
+    return hipGetLastError();
+}
+
+// The depth split's work items (cuts at equal splat counts, then their heaviest-first order), from
+// the setup's column counts and segment counts. Planned by the forward that uses them: with the
+// saturation exit (the default) the forward composites each tile in one item.
+static hipError_t plan_items(const RasterWs& r, int ntiles, hipStream_t s, const Views& vs) {
+    hipLaunchKernelGGL(k_plan_cuts, dim3(ntiles, vs.count), dim3(64), 0, s, r.weights,
+                       (const uint16_t*)r.colcnt, r.wpr / COL_WORDS, ntiles,
+                       (const int32_t*)r.tile_k, (const int32_t*)r.tile_first, r.items, r.item_w,
+                       vs.ws);
+    hipLaunchKernelGGL(k_plan_items, dim3(1, vs.count), dim3(NBUCKETS), 0, s,
+                       (const uint32_t*)r.item_w, ntiles, (const unsigned long long*)r.counters,
+                       r.item_order, vs.ws);
     return hipGetLastError();
 }
 
@@ -1813,6 +1818,10 @@ hipError_t launch_raster_fwd(const gs_config& cfg, int width, int height, int n,
     // depth split (at-rest state, no T-culling, no counters) serves the full walk
     const bool freeze = rfmt < 0 && !tcull && !out_cov && !(cfg.flags & GS_FLAG_COMPOSITE_ALL);
     const bool split = r.split && rfmt < 0 && !tcull && !instr && !freeze;
+    if (split) {
+        const hipError_t e0 = plan_items(r, ntiles, s, vs);
+        if (e0 != hipSuccess) return e0;
+    }
     FwdKernel k = V > 1 ? fwd_kernel<true>(rfmt, tcull, instr) : fwd_kernel<false>(rfmt, tcull, instr);
     hipLaunchKernelGGL(k, dim3(split ? ITEMS_PER_TILE * ntiles : ntiles, V), dim3(NT), 0, s, n,
                        n_visible,

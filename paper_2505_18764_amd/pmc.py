@@ -252,3 +252,54 @@ def atomic_summary(path: str, out_md: str, command: str, workload: str, top: int
     with open(os.path.join(os.path.dirname(out_md), "atomics.json"), "w") as fh:
         json.dump(js, fh, indent=1)
     return res
+
+
+STALL_COUNTERS = (("SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                   "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+                   "SQ_LDS_BANK_CONFLICT"),
+                  ("SQ_THREAD_CYCLES_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU",
+                   "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_MISC", "SQ_INSTS_BRANCH", "SQ_WAVES",
+                   "SQ_INSTS_SMEM"))
+
+
+def stall_summary(paths, out_md: str, commands, workload: str, top: int = 6) -> dict:
+    """Where the waves of each kernel spend their time, from two counter passes: the shares of
+    resident wave-cycles (SQ_WAVE_CYCLES) spent waiting on a dependency (SQ_WAIT_ANY), ready but
+    not issued (SQ_WAIT_INST_ANY), and issuing VALU, scalar, LDS and other instructions; and the
+    active lanes per VALU instruction (SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU)."""
+    m1, m2 = counter_means(paths[0]), counter_means(paths[1])
+    res = {}
+    lines = [f"# Wave time by state: {workload}", "",
+             "Commands (on one MI355X; `$R` is the repository root, `$OUT` any scratch directory):",
+             "", "```", *commands, "```", "",
+             "Shares of the resident wave-cycles (SQ_WAVE_CYCLES) of each kernel: waiting on a",
+             "dependency such as a memory result or a barrier (SQ_WAIT_ANY), ready but not issued",
+             "because another wave had the issue slot (SQ_WAIT_INST_ANY), and issuing VALU, scalar",
+             "(SALU and SMEM), LDS and miscellaneous instructions (SQ_ACTIVE_INST_*, from the second",
+             "pass, scaled by that pass's SQ_ACTIVE_INST_VALU to the first's). Lanes per VALU",
+             "instruction = SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU (64 = no idle lanes).", "",
+             "| kernel | mean us | wait (dependency) | wait (issue) | VALU | scalar | LDS | misc "
+             "| lanes per VALU |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(set(m1) & set(m2), key=lambda k: -m1[k]["_dur_ns"] * m1[k]["_calls"])[:top]:
+        a, b = m1[k], m2[k]
+        wc = a.get("SQ_WAVE_CYCLES", 0.0)
+        if not wc or not b.get("SQ_ACTIVE_INST_VALU"):
+            continue
+        sc = a["SQ_ACTIVE_INST_VALU"] / b["SQ_ACTIVE_INST_VALU"]
+        r = {"wait_dependency": a["SQ_WAIT_ANY"] / wc, "wait_issue": a["SQ_WAIT_INST_ANY"] / wc,
+             "valu": a["SQ_ACTIVE_INST_VALU"] / wc,
+             "scalar": b.get("SQ_ACTIVE_INST_SCA", 0.0) * sc / wc,
+             "lds": a.get("SQ_ACTIVE_INST_LDS", 0.0) / wc,
+             "misc": b.get("SQ_ACTIVE_INST_MISC", 0.0) * sc / wc,
+             "lanes_per_valu": b.get("SQ_THREAD_CYCLES_VALU", 0.0) / b["SQ_ACTIVE_INST_VALU"],
+             "mean_ns": a["_dur_ns"]}
+        res[k] = r
+        lines.append(f"| `{k}` | {a['_dur_ns'] / 1e3:.1f} | {r['wait_dependency']:.2f} | "
+                     f"{r['wait_issue']:.2f} | {r['valu']:.2f} | {r['scalar']:.2f} | "
+                     f"{r['lds']:.2f} | {r['misc']:.2f} | {r['lanes_per_valu']:.1f} |")
+    h = source_hash()
+    lines += ["", f"Source hash of the kernels measured: `{h}`."]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return res
