@@ -198,7 +198,7 @@ def project(means3d, scales, quats, opacities, sh, cam, cfg: RasterConfig, ws: W
                rgb=torch.empty(*lead, n, 3, device=dev), depth=torch.empty(*lead, n, device=dev),
                keys=torch.empty(*lead, n, dtype=torch.int32, device=dev),
                ids=torch.empty(*lead, n, dtype=torch.int32, device=dev),
-               n_visible=torch.zeros(V, dtype=torch.int32, device=dev))
+               n_visible=torch.empty(V, dtype=torch.int32, device=dev))   # written by the call
     cm0 = cm[0] if is_views(cam) else cm
     b, nb = _ws_args(ws, max(L.gs_workspace_size("preprocess", n, cm0.width, cm0.height, cc), 256))
     L.gs_preprocess(cm, cc, n, means3d, scales, quats, opacities, sh, out["means2d"],
@@ -219,7 +219,7 @@ def prepare_2d(means2d, conics, opacities, rgb, depth, width, height, cfg: Raste
     means2d, conics, opacities, rgb, depth = map(_c32, (means2d, conics, opacities, rgb, depth))
     keys = torch.empty(n, dtype=torch.int32, device=dev)
     ids = torch.empty(n, dtype=torch.int32, device=dev)
-    nvis = torch.zeros(1, dtype=torch.int32, device=dev)
+    nvis = torch.empty(1, dtype=torch.int32, device=dev)            # written by the call
     b, nb = _ws_args(ws, L.gs_workspace_size("prepare_2d", n, width, height, cc))
     L.gs_prepare_2d(cm, cc, n, means2d, conics, opacities, depth, keys, ids, nvis, b, nb,
                     _stream(dev))
