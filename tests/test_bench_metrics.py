@@ -35,3 +35,49 @@ def test_roofline_kernels_are_in_the_traffic_summary():
     d = json.load(open(os.path.join(os.path.dirname(bench.__file__), "profiles", "traffic.json")))
     for k in bench.FWD_KERNELS + bench.BWD_KERNELS:
         assert k in d, k
+
+
+def _counter_db(path, rows):
+    """A rocprofv3-shaped counter database: rows of (kernel, counter, value, dispatch, ns)."""
+    import sqlite3
+    con = sqlite3.connect(path)
+    con.execute("create table counters_collection (kernel_name text, counter_name text, "
+                "value real, dispatch_id integer, duration real)")
+    con.executemany("insert into counters_collection values (?, ?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_counter_summaries_from_a_synthetic_database(tmp_path):
+    """The counter summaries bench.py commits: per-dispatch values summed over counter instances
+    and averaged over dispatches; the wave-state shares; the atomic rate; the micro kernel's
+    measured (longest) launch instead of the mean with its warm-up."""
+    from paper_2505_18764_amd import pmc
+    k = "void gsr::k_raster_bwd<-1, false, false, true>(int, float*)"
+    s1 = [(k, "SQ_WAVE_CYCLES", 500.0, d, 1000.0) for d in (1, 2)] + \
+         [(k, "SQ_WAVE_CYCLES", 500.0, d, 1000.0) for d in (1, 2)] + \
+         [(k, c, v, d, 1000.0) for d in (1, 2) for c, v in
+          (("SQ_WAIT_ANY", 400.0), ("SQ_WAIT_INST_ANY", 200.0), ("SQ_ACTIVE_INST_VALU", 250.0),
+           ("SQ_ACTIVE_INST_LDS", 10.0), ("SQ_BUSY_CYCLES", 1.0), ("SQ_WAIT_INST_LDS", 1.0),
+           ("SQ_LDS_BANK_CONFLICT", 0.0))]
+    s2 = [(k, c, v, d, 1000.0) for d in (1, 2) for c, v in
+          (("SQ_THREAD_CYCLES_VALU", 60.0 * 125.0), ("SQ_ACTIVE_INST_VALU", 125.0),
+           ("SQ_ACTIVE_INST_SCA", 50.0), ("SQ_ACTIVE_INST_MISC", 10.0), ("SQ_INSTS_VALU", 1.0),
+           ("SQ_INSTS_BRANCH", 1.0), ("SQ_WAVES", 1.0), ("SQ_INSTS_SMEM", 1.0))]
+    _counter_db(str(tmp_path / "s1.db"), s1)
+    _counter_db(str(tmp_path / "s2.db"), s2)
+    m = pmc.counter_means(str(tmp_path / "s1.db"))
+    kk = "k_raster_bwd<-1, false, false, true>"
+    assert m[kk]["SQ_WAVE_CYCLES"] == 1000.0 and m[kk]["_calls"] == 2   # two instances summed
+    r = pmc.stall_summary([str(tmp_path / "s1.db"), str(tmp_path / "s2.db")],
+                          str(tmp_path / "st.md"), ["cmd"], "w")[kk]
+    assert r["wait_dependency"] == pytest.approx(0.4) and r["wait_issue"] == pytest.approx(0.2)
+    assert r["valu"] == pytest.approx(0.25) and r["lanes_per_valu"] == pytest.approx(60.0)
+    assert r["scalar"] == pytest.approx(50.0 * 2.0 / 1000.0)     # scaled by the VALU ratio
+    mk = "void gsr::k_micro_atomic<0>(float*, unsigned int, int, float*)"
+    at = [(mk, "TCC_ATOMIC_sum", 10.0, 1, 100.0), (mk, "TCC_ATOMIC_sum", 160.0, 2, 1600.0)] + \
+         [(k, "TCC_ATOMIC_sum", 50.0, d, 1000.0) for d in (3, 4)]
+    _counter_db(str(tmp_path / "at.db"), at)
+    a = pmc.atomic_summary(str(tmp_path / "at.db"), str(tmp_path / "at.md"), "cmd", "w")
+    assert a["k_micro_atomic<0>"]["TCC_ATOMIC_sum"] == 160.0          # the measured launch
+    assert a[kk]["l2_atomics_per_s"] == pytest.approx(50.0 / 1e-6)
